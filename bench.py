@@ -1,0 +1,180 @@
+"""Benchmark: truncated vs full product on one MI355X.
+
+A step is one low product, one high product and one full product of the same
+two n-bit operands (n = 2^24 by default: uniform random 64-bit limbs from a
+fixed seed), inputs resident in HBM.  Prints one JSON line with
+
+* value: whole-step operand throughput, 3 n bits / step time, in Mbit/s;
+* per-kind time and Mbit/s, and the lo/full and hi/full time ratios;
+* roofline: algorithmic bytes / time of the dominant kernel, timed with HIP
+  events on the launch stream, against the 8 TB/s HBM peak;
+* cpu_baseline: the CPU oracle (Karatsuba on 64-bit limbs) computing the
+  same three products for one operand pair, timed on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "mul_hi/mul_lo vs mul_full time ratio; operand Mbit/s; p50/p99 latency batched"
+
+
+def kernel_bytes(plan, n_bits, kind):
+    """Algorithmic HBM bytes per launch of each kernel (reads + writes).
+
+    With N real coefficients and M = N/2 complex points: K1 reads both
+    operands (n/8 bytes each) and writes two packed spectra (2 M 16 = 16 N
+    bytes); K2 reads them (16 N) and writes the product spectrum (8 N); K3
+    reads and writes one complex array (8 N + 8 N); K4 reads the real
+    convolution (8 N) and writes the result limbs."""
+    N = plan["N"]
+    L = (n_bits + 63) // 64
+    out = 16 * L if kind == "full" else 8 * L
+    return {"split_map_colfft": 2 * 8 * L + 16 * N,
+            "rowfft_pointwise_rowifft": 24 * N,
+            "col_ifft": 16 * N,
+            "backmap_round_carry": 8 * N + out}
+
+
+def cpu_baseline(n_bits, threads):
+    import oracle
+    from paper_1703_00640_amd import inputs
+    u, v = inputs.operand_pair(n_bits, 2)
+    t0 = time.perf_counter()
+    oracle.mul_lo(u, v, n_bits, threads)
+    oracle.mul_hi(u, v, n_bits, threads)
+    oracle.mul_full(u, v, n_bits, threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(3 * n_bits / dt / 1e6, 3), "unit": "operand Mbit/s",
+            "cores": threads, "kind": "oracle",
+            "sample": "one lo + hi + full product of one n=%d operand pair (%.1f s)" % (n_bits, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--log2n", type=int, default=24)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1703_00640_amd as tm
+    from paper_1703_00640_amd import inputs
+
+    n = 1 << args.log2n
+    L = n // 64
+    dev = torch.device("cuda:0")
+    u, v = inputs.operand_pair(n, 2)
+    du = torch.from_numpy(u.view(np.int64)).to(dev)
+    dv = torch.from_numpy(v.view(np.int64)).to(dev)
+    kinds = ("lo", "hi", "full")
+    plans = {k: tm.plan(k, n) for k in kinds}
+    ws = {k: torch.empty(plans[k]["workspace_bytes"], dtype=torch.uint8, device=dev) for k in kinds}
+    outs = {k: torch.empty(2 * L if k == "full" else L, dtype=torch.int64, device=dev) for k in kinds}
+    guards = {k: tm.new_guard(dev) for k in kinds}
+    stream = torch.cuda.current_stream(dev)
+
+    def one(k):
+        tm.mul(k, du, dv, n, out=outs[k], workspace=ws[k], stream=stream, guard=guards[k])
+
+    for _ in range(args.warmup):
+        for k in kinds:
+            one(k)
+    torch.cuda.synchronize()
+
+    # whole step
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        for k in kinds:
+            one(k)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms_step = e0.elapsed_time(e1) / args.steps
+
+    # per kind (separate timed loops, same stream)
+    per = {}
+    for k in kinds:
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.steps):
+            one(k)
+        b.record(stream)
+        torch.cuda.synchronize()
+        per[k] = a.elapsed_time(b) / args.steps
+
+    # per kernel, HIP events recorded by the library between its launches
+    stage = {k: {} for k in kinds}
+    reps = max(5, min(args.steps, 20))
+    for k in kinds:
+        acc = {}
+        for _ in range(reps):
+            for name, ms in tm.profile_stages(k, du, dv, n, outs[k], ws[k], stream=stream):
+                acc.setdefault(name, []).append(ms)
+        stage[k] = {name: float(np.mean(v)) for name, v in acc.items()}
+
+    best = None
+    for k in kinds:
+        nb = kernel_bytes(plans[k], n, k)
+        for name, ms in stage[k].items():
+            if best is None or ms > best[2]:
+                best = (k, name, ms, nb[name])
+    k_dom, name_dom, ms_dom, bytes_dom = best
+    achieved = bytes_dom / (ms_dom * 1e-3) / 1e9
+
+    gd = {k: tm.read_guard(guards[k]).as_dict() for k in kinds}
+    result = {
+        "metric": METRIC,
+        "value": round(3 * n / (ms_step * 1e-3) / 1e6, 3),
+        "unit": "operand Mbit/s (lo+hi+full step)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: uniform random limbs, PCG64 seeds 4 and 5",
+        "config": {"workload": "one mul_lo, mul_hi and mul_full of two n=2^%d-bit operands" % args.log2n,
+                   "n_bits": n, "limbs": L,
+                   "plans": {k: {x: plans[k][x] for x in ("b", "lam", "N", "L1", "L2", "via_full")}
+                             for k in kinds}},
+        "ms": {k: round(per[k], 5) for k in kinds},
+        "mbit_s": {k: round(n / (per[k] * 1e-3) / 1e6, 2) for k in kinds},
+        "ratio_lo_full": round(per["lo"] / per["full"], 4),
+        "ratio_hi_full": round(per["hi"] / per["full"], 4),
+        "stage_ms": {k: {s: round(t, 5) for s, t in stage[k].items()} for k in kinds},
+        "guard_max_dist": {k: gd[k]["max_dist"] for k in kinds},
+        "guard_flags": {k: gd[k]["flags"] for k in kinds},
+        "roofline": {"bound": "hbm", "kernel": "%s:%s" % (k_dom, name_dom),
+                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": bytes_dom, "ms_per_launch": round(ms_dom, 5)},
+        "wall_s_timed": round(wall, 3),
+    }
+    if not args.no_cpu:
+        threads = min(16, os.cpu_count() or 1)
+        result["cpu_baseline"] = cpu_baseline(n, threads)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,199 @@
+/*
+ * tmul.h - truncated integer multiplication on AMD Instinct MI355X (gfx950).
+ *
+ * Implements the hot path of D. Harvey, "Faster truncated integer
+ * multiplication" (arXiv 1703.00640): the low product uv mod 2^n and the high
+ * product (the top n bits of uv, possibly one too large) of two n-bit
+ * integers through a real cyclic convolution of length N, instead of the
+ * length 2N that the full 2n-bit product needs (Algorithms "low product" and
+ * "high product"), and the full product itself (Algorithm "full product").
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Integers are little-endian arrays of uint64_t limbs in DEVICE memory.
+ *   An n-bit operand has L = ceil(n/64) limbs; bits at positions >= n are
+ *   ignored (the library masks them).
+ * - Outputs: low and high product -> L limbs, bits >= n cleared; full
+ *   product -> 2L limbs.
+ * - The caller owns u, v, w and the workspace.  w must not overlap u, v or
+ *   the workspace; u == v (squaring) is allowed.  Workspace size comes from
+ *   tm_workspace_bytes() and must be at least that many bytes, 256-byte
+ *   aligned.
+ * - All calls are asynchronous on the given HIP stream (NULL = default
+ *   stream) and do not synchronise, except tm_mul_checked().  Two calls may
+ *   run concurrently only with distinct workspaces.
+ * - Errors are reported through the return code only; nothing is thrown and
+ *   nothing exits.  After TM_ERR_HIP, tm_last_error() describes the failing
+ *   HIP call (per thread).
+ * - The library keeps one device-side cache per (device, transform length):
+ *   the FFT twiddle tables, built on first use (this first call synchronises
+ *   its stream once).  tm_release_caches() frees them.
+ */
+#ifndef TMUL_H
+#define TMUL_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TM_FULL = 0, /* uv                                   (Algorithm full)  */
+    TM_LO = 1,   /* uv mod 2^n                           (Algorithm low)   */
+    TM_HI = 2    /* w in [0,2^n] with |uv - 2^n w| < 2^n (Algorithm high)  */
+} tm_kind;
+
+typedef enum {
+    TM_OK = 0,
+    TM_ERR_INVALID = 1,     /* null pointer, n = 0, bad kind, workspace too small */
+    TM_ERR_HIP = 2,         /* a HIP launch or runtime call failed               */
+    TM_ERR_PRECISION = 3,   /* tm_mul_checked: the rounding guard tripped even
+                               after the fallback plan                          */
+    TM_ERR_UNSUPPORTED = 4  /* n beyond the planner's limits                    */
+} tm_status;
+
+/* Rounding guard, written on the device by every multiplication.
+ * x ranges over every rounded coefficient: 2^b times the back-mapped
+ * convolution for the truncated products (round(2^b W-bar_i) in the
+ * algorithms), the convolution itself for the full product.
+ * flags: bit0 max_dist >= 0.25; bit1 max_abs >= 2^50 (|x| so large that
+ * distances to integers stop being meaningful); bit2 the lowest coefficient
+ * is not a multiple of 2^b (it must be, by the cancellation propositions);
+ * bit3 a carry look-back wait hit its spin limit (result invalid). */
+typedef struct {
+    double max_dist;   /* max |x - rint(x)|                                  */
+    double max_abs;    /* max |x|                                            */
+    uint32_t flags;
+    uint32_t b;        /* digit size used                                    */
+    uint32_t lambda;   /* series length used (0 for the full product)        */
+    uint32_t kind;     /* tm_kind of the plan actually run                   */
+    uint64_t N;        /* convolution length (real)                          */
+} tm_guard;
+
+#define TM_GUARD_DIST 1u
+#define TM_GUARD_ABS 2u
+#define TM_GUARD_C0 4u
+#define TM_GUARD_SPIN 8u
+
+/* Plan chosen for (kind, n): deterministic, a pure function of (kind, n). */
+typedef struct {
+    uint32_t kind;          /* requested kind                                     */
+    uint32_t via_full;      /* 1 if a truncated product is served by the full-
+                               product kernels plus extraction (small n)         */
+    uint32_t b;             /* digit size                                         */
+    uint32_t lambda;        /* series terms for the ring maps (0 if none)         */
+    uint64_t n_bits;
+    uint64_t N;             /* real convolution length: the ring degree N for the
+                               truncated products, 2N (paper notation) for full  */
+    uint64_t digits;        /* digits per operand: N (low), N+1 (high), N (full,
+                               paper notation)                                    */
+    uint64_t M;             /* complex FFT length = N/2                           */
+    uint32_t L1, L2;        /* M = L1 * L2: column and row sub-transform lengths  */
+    uint64_t workspace_bytes;
+} tm_plan_info;
+
+/* One request of a batch: w = product(kind, u, v) on n_bits-bit operands. */
+typedef struct {
+    uint32_t kind;          /* tm_kind */
+    uint32_t reserved;
+    uint64_t n_bits;
+    const uint64_t* u;
+    const uint64_t* v;
+    uint64_t* w;
+} tm_request;
+
+/* Bytes of workspace a call of (kind, n_bits) needs; 0 if unsupported. */
+size_t tm_workspace_bytes(tm_kind kind, uint64_t n_bits);
+
+/* Fill *out with the plan used for (kind, n_bits).  Host only, no GPU work. */
+tm_status tm_plan_query(tm_kind kind, uint64_t n_bits, tm_plan_info* out);
+
+/*
+ * w <- product of kind `kind` of u and v (n_bits-bit operands).
+ * Full product: Algorithm "full product" (Section 2.2).
+ * Low product: Algorithm "low product" (Section 3.4), with the ring maps of
+ *   Propositions "approximating alpha*" and "approximating beta*" and the
+ *   cancellation trick of Proposition "low-cancel".
+ * High product: Algorithm "high product" (Section 4.4), with the maps of
+ *   Propositions "approximating gamma-dagger" / "approximating delta-dagger"
+ *   and Proposition "high-cancel"; returns round(t), one of the at most two
+ *   allowed values.
+ * guard_dev: device pointer to a tm_guard to receive the rounding guard, or
+ *   NULL (then the guard lives in the workspace).
+ */
+tm_status tm_mul(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v,
+                 uint64_t n_bits, void* workspace, size_t workspace_bytes,
+                 hipStream_t stream, tm_guard* guard_dev);
+
+tm_status tm_mul_full(uint64_t* w, const uint64_t* u, const uint64_t* v, uint64_t n_bits,
+                      void* workspace, size_t workspace_bytes, hipStream_t stream,
+                      tm_guard* guard_dev);
+tm_status tm_mul_lo(uint64_t* w, const uint64_t* u, const uint64_t* v, uint64_t n_bits,
+                    void* workspace, size_t workspace_bytes, hipStream_t stream,
+                    tm_guard* guard_dev);
+tm_status tm_mul_hi(uint64_t* w, const uint64_t* u, const uint64_t* v, uint64_t n_bits,
+                    void* workspace, size_t workspace_bytes, hipStream_t stream,
+                    tm_guard* guard_dev);
+
+/* Workspace for a batch: the largest single-request workspace. */
+size_t tm_workspace_bytes_batched(const tm_request* reqs, size_t count);
+
+/*
+ * Run `count` requests (host array of descriptors with device pointers) on
+ * one stream, in order, sharing one workspace of
+ * tm_workspace_bytes_batched() bytes.  guards_dev: device array of `count`
+ * tm_guard, or NULL.
+ */
+tm_status tm_mul_batched(const tm_request* reqs, size_t count, void* workspace,
+                         size_t workspace_bytes, hipStream_t stream, tm_guard* guards_dev);
+
+/*
+ * Like tm_mul, then synchronises the stream and reads the guard.  If it
+ * tripped, recomputes with the fallback plan (smaller digits, see
+ * tm_workspace_bytes_checked) and checks again.  *guard_host (may be NULL)
+ * receives the guard of the last run.  Returns TM_ERR_PRECISION if the
+ * fallback tripped too.
+ */
+size_t tm_workspace_bytes_checked(tm_kind kind, uint64_t n_bits);
+tm_status tm_mul_checked(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v,
+                         uint64_t n_bits, void* workspace, size_t workspace_bytes,
+                         hipStream_t stream, tm_guard* guard_host);
+
+/*
+ * Diagnostic: run the path up to rounding and write the rounded coefficients
+ * c_i (int64, `coeffs_len` = plan.N for the full and low product, plan.N+1
+ * for the high product) and the unrounded x_i (double, same length, may be
+ * NULL) to device buffers.  c_i = round(2^b W-bar_i) of the truncated
+ * algorithms (equal to 2^b L_i resp. 2^b H_i of the cancellation
+ * propositions when the guard passes), c_i = round(W-bar_i) for the full
+ * product.  No carry propagation.  Same workspace as tm_mul.
+ */
+tm_status tm_coefficients(tm_kind kind, int64_t* coeffs, double* x, uint64_t coeffs_len,
+                          const uint64_t* u, const uint64_t* v, uint64_t n_bits,
+                          void* workspace, size_t workspace_bytes, hipStream_t stream,
+                          tm_guard* guard_dev);
+
+/*
+ * Measurement: run one multiplication with HIP events recorded on `stream`
+ * between its kernels, synchronise, and write the elapsed milliseconds of
+ * each kernel to stage_ms[0..*n_stages) (capacity `cap`) and their names to
+ * names[i] (static strings; may be NULL).  The stages are: split+map+column
+ * FFT, row FFT+pointwise+inverse row FFT, inverse column FFT,
+ * back-map+round+carry.
+ */
+tm_status tm_profile_stages(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v,
+                            uint64_t n_bits, void* workspace, size_t workspace_bytes,
+                            hipStream_t stream, float* stage_ms, const char** names,
+                            int cap, int* n_stages);
+
+const char* tm_status_string(tm_status s);
+const char* tm_last_error(void);
+void tm_release_caches(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TMUL_H */

@@ -1,0 +1,279 @@
+"""Truncated integer multiplication on AMD MI355X: Python binding of libtmul.
+
+Thin ctypes marshalling over the C ABI in ``include/tmul.h``: every step of
+the computation runs in the library's HIP kernels.  PyTorch provides device
+memory and streams only.  Operands are contiguous ``torch.uint64`` (or
+``torch.int64``, same bits) tensors of ``ceil(n/64)`` little-endian limbs on
+one GPU.
+
+The library must have been built (``paper_1703_00640_amd.build.build()`` or
+``__graft_entry__.build()``); importing works without it, calling does not.
+"""
+import ctypes
+import os
+
+import torch
+
+__all__ = ["mul", "mul_lo", "mul_hi", "mul_full", "mul_batched", "mul_checked",
+           "coefficients", "profile_stages", "plan", "workspace_bytes", "Guard",
+           "TmulError", "KINDS", "library_path"]
+
+KINDS = {"full": 0, "lo": 1, "hi": 2}
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libtmul.so")
+_lib = None
+
+
+class TmulError(RuntimeError):
+    pass
+
+
+class Guard(ctypes.Structure):
+    """Rounding guard written by every multiplication (see tmul.h)."""
+    _fields_ = [("max_dist", ctypes.c_double), ("max_abs", ctypes.c_double),
+                ("flags", ctypes.c_uint32), ("b", ctypes.c_uint32),
+                ("lam", ctypes.c_uint32), ("kind", ctypes.c_uint32),
+                ("N", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("via_full", ctypes.c_uint32),
+                ("b", ctypes.c_uint32), ("lam", ctypes.c_uint32),
+                ("n_bits", ctypes.c_uint64), ("N", ctypes.c_uint64),
+                ("digits", ctypes.c_uint64), ("M", ctypes.c_uint64),
+                ("L1", ctypes.c_uint32), ("L2", ctypes.c_uint32),
+                ("workspace_bytes", ctypes.c_uint64)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("n_bits", ctypes.c_uint64), ("u", ctypes.c_void_p),
+                ("v", ctypes.c_void_p), ("w", ctypes.c_void_p)]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(library_path):
+        raise TmulError("libtmul.so is not built: run __graft_entry__.build()")
+    lib = ctypes.CDLL(library_path)
+    P = ctypes.c_void_p
+    U64, SZ, I32 = ctypes.c_uint64, ctypes.c_size_t, ctypes.c_int
+    lib.tm_workspace_bytes.argtypes = [I32, U64]
+    lib.tm_workspace_bytes.restype = SZ
+    lib.tm_workspace_bytes_checked.argtypes = [I32, U64]
+    lib.tm_workspace_bytes_checked.restype = SZ
+    lib.tm_workspace_bytes_batched.argtypes = [P, SZ]
+    lib.tm_workspace_bytes_batched.restype = SZ
+    lib.tm_plan_query.argtypes = [I32, U64, ctypes.POINTER(_PlanInfo)]
+    lib.tm_mul.argtypes = [I32, P, P, P, U64, P, SZ, P, P]
+    for name in ("tm_mul_full", "tm_mul_lo", "tm_mul_hi"):
+        getattr(lib, name).argtypes = [P, P, P, U64, P, SZ, P, P]
+    lib.tm_mul_batched.argtypes = [P, SZ, P, SZ, P, P]
+    lib.tm_mul_checked.argtypes = [I32, P, P, P, U64, P, SZ, P, ctypes.POINTER(Guard)]
+    lib.tm_coefficients.argtypes = [I32, P, P, U64, P, P, U64, P, SZ, P, P]
+    lib.tm_profile_stages.argtypes = [I32, P, P, P, U64, P, SZ, P,
+                                      ctypes.POINTER(ctypes.c_float),
+                                      ctypes.POINTER(ctypes.c_char_p), I32,
+                                      ctypes.POINTER(I32)]
+    for name in ("tm_plan_query", "tm_mul", "tm_mul_full", "tm_mul_lo", "tm_mul_hi",
+                 "tm_mul_batched", "tm_mul_checked", "tm_coefficients", "tm_profile_stages"):
+        getattr(lib, name).restype = I32
+    lib.tm_status_string.argtypes = [I32]
+    lib.tm_status_string.restype = ctypes.c_char_p
+    lib.tm_last_error.argtypes = []
+    lib.tm_last_error.restype = ctypes.c_char_p
+    lib.tm_release_caches.argtypes = []
+    lib.tm_release_caches.restype = None
+    _lib = lib
+    return lib
+
+
+def _check(status, what):
+    if status != 0:
+        lib = _load()
+        raise TmulError("%s: %s (%s)" % (what, lib.tm_status_string(status).decode(),
+                                          lib.tm_last_error().decode()))
+
+
+def _kind(kind):
+    if isinstance(kind, str):
+        return KINDS[kind]
+    return int(kind)
+
+
+def nlimbs(n_bits):
+    return (int(n_bits) + 63) // 64
+
+
+def plan(kind, n_bits):
+    """The plan (b, lambda, N, FFT split, workspace) used for (kind, n_bits)."""
+    info = _PlanInfo()
+    _check(_load().tm_plan_query(_kind(kind), int(n_bits), ctypes.byref(info)), "plan")
+    return {k: getattr(info, k) for k, _ in _PlanInfo._fields_}
+
+
+def workspace_bytes(kind, n_bits, checked=False):
+    lib = _load()
+    f = lib.tm_workspace_bytes_checked if checked else lib.tm_workspace_bytes
+    nb = f(_kind(kind), int(n_bits))
+    if nb == 0:
+        raise TmulError("unsupported (kind, n_bits) = (%s, %d)" % (kind, n_bits))
+    return nb
+
+
+def _dev_ptr(t, L, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TmulError("%s must be a CUDA/HIP tensor" % name)
+    if t.dtype not in (torch.uint64, torch.int64) or not t.is_contiguous():
+        raise TmulError("%s must be a contiguous 64-bit integer tensor" % name)
+    if t.numel() < L:
+        raise TmulError("%s has %d limbs, needs %d" % (name, t.numel(), L))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream, device):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _workspace(nbytes, device, workspace):
+    if workspace is None:
+        return torch.empty(nbytes, dtype=torch.uint8, device=device)
+    if workspace.numel() * workspace.element_size() < nbytes:
+        raise TmulError("workspace too small: %d < %d bytes" % (
+            workspace.numel() * workspace.element_size(), nbytes))
+    return workspace
+
+
+def new_guard(device):
+    """A device buffer for one tm_guard (read it with read_guard)."""
+    return torch.zeros(ctypes.sizeof(Guard), dtype=torch.uint8, device=device)
+
+
+def read_guard(buf):
+    raw = bytes(buf.detach().cpu().numpy().tobytes())
+    return Guard.from_buffer_copy(raw[:ctypes.sizeof(Guard)])
+
+
+def mul(kind, u, v, n_bits, out=None, workspace=None, stream=None, guard=None):
+    """w = product of ``kind`` ('lo', 'hi' or 'full') of u and v (n_bits each).
+
+    Returns the output tensor (L limbs for lo/hi, 2L for full), enqueued on
+    ``stream`` (default: torch's current stream).  ``guard`` may be a tensor
+    from new_guard() to receive the rounding guard."""
+    k = _kind(kind)
+    L = nlimbs(n_bits)
+    dev = u.device
+    pu, pv = _dev_ptr(u, L, "u"), _dev_ptr(v, L, "v")
+    nout = 2 * L if k == 0 else L
+    if out is None:
+        out = torch.empty(nout, dtype=torch.uint64, device=dev)
+    pw = _dev_ptr(out, nout, "out")
+    nb = workspace_bytes(k, n_bits)
+    ws = _workspace(nb, dev, workspace)
+    g = ctypes.c_void_p(guard.data_ptr()) if guard is not None else None
+    _check(_load().tm_mul(k, pw, pu, pv, int(n_bits), ctypes.c_void_p(ws.data_ptr()),
+                          ws.numel() * ws.element_size(), _stream_ptr(stream, dev), g), "tm_mul")
+    return out
+
+
+def mul_lo(u, v, n_bits, **kw):
+    return mul("lo", u, v, n_bits, **kw)
+
+
+def mul_hi(u, v, n_bits, **kw):
+    return mul("hi", u, v, n_bits, **kw)
+
+
+def mul_full(u, v, n_bits, **kw):
+    return mul("full", u, v, n_bits, **kw)
+
+
+def mul_batched(requests, workspace=None, stream=None, guards=None):
+    """requests: list of (kind, u, v, n_bits, out) with device tensors; runs
+    them in order on one stream with a shared workspace."""
+    if not requests:
+        return
+    arr = (_Request * len(requests))()
+    dev = requests[0][1].device
+    for i, (kind, u, v, n_bits, out) in enumerate(requests):
+        L = nlimbs(n_bits)
+        k = _kind(kind)
+        arr[i].kind = k
+        arr[i].n_bits = int(n_bits)
+        arr[i].u = _dev_ptr(u, L, "u").value
+        arr[i].v = _dev_ptr(v, L, "v").value
+        arr[i].w = _dev_ptr(out, 2 * L if k == 0 else L, "out").value
+    lib = _load()
+    nb = lib.tm_workspace_bytes_batched(ctypes.byref(arr), len(requests))
+    if nb == 0:
+        raise TmulError("unsupported request in batch")
+    ws = _workspace(nb, dev, workspace)
+    g = ctypes.c_void_p(guards.data_ptr()) if guards is not None else None
+    _check(lib.tm_mul_batched(ctypes.byref(arr), len(requests), ctypes.c_void_p(ws.data_ptr()),
+                              ws.numel() * ws.element_size(), _stream_ptr(stream, dev), g),
+           "tm_mul_batched")
+
+
+def mul_checked(kind, u, v, n_bits, out=None, workspace=None, stream=None):
+    """Multiply, synchronise, and fall back to smaller digits if the rounding
+    guard tripped.  Returns (out, Guard)."""
+    k = _kind(kind)
+    L = nlimbs(n_bits)
+    dev = u.device
+    nout = 2 * L if k == 0 else L
+    if out is None:
+        out = torch.empty(nout, dtype=torch.uint64, device=dev)
+    ws = _workspace(workspace_bytes(k, n_bits, checked=True), dev, workspace)
+    g = Guard()
+    _check(_load().tm_mul_checked(k, _dev_ptr(out, nout, "out"), _dev_ptr(u, L, "u"),
+                                  _dev_ptr(v, L, "v"), int(n_bits),
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                  _stream_ptr(stream, dev), ctypes.byref(g)), "tm_mul_checked")
+    return out, g
+
+
+def coefficients(kind, u, v, n_bits, with_x=True, workspace=None, stream=None):
+    """Rounded coefficients c_i (int64) and unrounded x_i (float64) of the
+    plan for (kind, n_bits), plus the guard (synchronises)."""
+    k = _kind(kind)
+    L = nlimbs(n_bits)
+    dev = u.device
+    pl = plan(k, n_bits)
+    ncoef = pl["N"] + (1 if (k == 2 and not pl["via_full"]) else 0)
+    c = torch.empty(ncoef, dtype=torch.int64, device=dev)
+    x = torch.empty(ncoef, dtype=torch.float64, device=dev) if with_x else None
+    ws = _workspace(workspace_bytes(k, n_bits), dev, workspace)
+    gb = new_guard(dev)
+    _check(_load().tm_coefficients(k, ctypes.c_void_p(c.data_ptr()),
+                                   ctypes.c_void_p(x.data_ptr()) if x is not None else None,
+                                   ncoef, _dev_ptr(u, L, "u"), _dev_ptr(v, L, "v"), int(n_bits),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                   _stream_ptr(stream, dev), ctypes.c_void_p(gb.data_ptr())),
+           "tm_coefficients")
+    torch.cuda.synchronize(dev)
+    return c, x, read_guard(gb)
+
+
+def profile_stages(kind, u, v, n_bits, out, workspace, stream=None):
+    """One multiplication with HIP events between its kernels on ``stream``;
+    returns [(stage_name, ms), ...] (synchronises)."""
+    k = _kind(kind)
+    L = nlimbs(n_bits)
+    cap = 8
+    ms = (ctypes.c_float * cap)()
+    names = (ctypes.c_char_p * cap)()
+    nst = ctypes.c_int(0)
+    nout = 2 * L if k == 0 else L
+    _check(_load().tm_profile_stages(k, _dev_ptr(out, nout, "out"), _dev_ptr(u, L, "u"),
+                                     _dev_ptr(v, L, "v"), int(n_bits),
+                                     ctypes.c_void_p(workspace.data_ptr()),
+                                     workspace.numel() * workspace.element_size(),
+                                     _stream_ptr(stream, u.device), ms, names, cap,
+                                     ctypes.byref(nst)), "tm_profile_stages")
+    return [(names[i].decode(), float(ms[i])) for i in range(nst.value)]

@@ -1,0 +1,192 @@
+// Workgroup-level FP64 complex DFTs on a tile held in LDS (gfx950).
+//
+// This is the building block of the Convolution step (Section 2.1: real
+// FFTs, pointwise product, inverse FFT).  A tile holds NB independent
+// sequences of length P; a Stockham autosort schedule of radix-3/4/8/2
+// stages transforms all of them in place, one LDS round trip per stage.
+// Twiddles come from a two-level table of exp(-2 pi i e / M) (M = whole
+// transform length), so every twiddle is the product of two correctly
+// rounded table entries.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tmul {
+
+struct Tw {
+    const double2* lo;   // lo[e0] = exp(-2 pi i e0 / M), e0 < 2^shift
+    const double2* hi;   // hi[e1] = exp(-2 pi i e1 2^shift / M)
+    uint32_t shift;
+    uint32_t mask;
+};
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ double2 mul_mi(double2 a)
+{
+    return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+// exp(-2 pi i e / M), or its conjugate for the inverse direction
+template <bool INV>
+__device__ __forceinline__ double2 tw_get(const Tw& t, uint32_t e)
+{
+    double2 w = cmul(t.lo[e & t.mask], t.hi[e >> t.shift]);
+    return INV ? cconj(w) : w;
+}
+
+// ------------------------------------------------------------- codelets
+
+template <bool INV>
+__device__ __forceinline__ void dft2(double2* v)
+{
+    double2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft3(double2* v)
+{
+    const double h = 0.86602540378443864676;  // sin(2 pi / 3)
+    double2 s = cadd(v[1], v[2]);
+    double2 d = csub(v[1], v[2]);
+    double2 t = make_double2(fma(-0.5, s.x, v[0].x), fma(-0.5, s.y, v[0].y));
+    double2 u = mul_mi<INV>(cscale(d, h));  // -i h d (forward)
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(t, u);
+    v[2] = csub(t, u);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(double2* v)
+{
+    double2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    double2 t2 = cadd(v[1], v[3]), t3 = mul_mi<INV>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(double2* v)
+{
+    const double c = 0.70710678118654752440;
+    double2 e[4] = {v[0], v[2], v[4], v[6]};
+    double2 o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<INV>(e);
+    dft4<INV>(o);
+    if (!INV) {
+        o[1] = make_double2(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));
+        o[2] = make_double2(o[2].y, -o[2].x);
+        o[3] = make_double2(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y));
+    } else {
+        o[1] = make_double2(c * (o[1].x - o[1].y), c * (o[1].x + o[1].y));
+        o[2] = make_double2(-o[2].y, o[2].x);
+        o[3] = make_double2(-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y));
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        v[k] = cadd(e[k], o[k]);
+        v[k + 4] = csub(e[k], o[k]);
+    }
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dftR(double2* v)
+{
+    if constexpr (R == 2) dft2<INV>(v);
+    else if constexpr (R == 3) dft3<INV>(v);
+    else if constexpr (R == 4) dft4<INV>(v);
+    else dft8<INV>(v);
+}
+
+// radix of the next stage given the remaining length
+constexpr int pick_radix(int rem)
+{
+    return rem % 3 == 0 ? 3 : rem == 16 ? 4 : rem % 8 == 0 ? 8 : rem % 4 == 0 ? 4 : 2;
+}
+
+// Element (j, c) of the tile: sequence c, position j.
+//   COLS: sequences interleaved (address j*NB + c)  - column tiles
+//   rows: sequences contiguous  (address c*RS + j)   - row tiles
+template <bool COLS, int NB, int RS>
+__device__ __forceinline__ int tile_addr(int j, int c)
+{
+    return COLS ? j * NB + c : c * RS + j;
+}
+
+// One Stockham stage of radix R after NS points have been combined.
+template <int P, int R, int NS, int NB, int NT, bool INV, bool COLS, int RS>
+__device__ __forceinline__ void fft_stage(double2* buf, const Tw& tw, uint32_t tscale)
+{
+    constexpr int BF = P / R;
+    constexpr int TOT = BF * NB;
+    constexpr int PER = (TOT + NT - 1) / NT;
+    constexpr uint32_t ESTEP = P / (NS * R);
+    double2 v[PER][R];
+    int jj[PER], cc[PER];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        int idx = tid + q * NT;
+        jj[q] = COLS ? idx / NB : idx % BF;
+        cc[q] = COLS ? idx % NB : idx / BF;
+        if (TOT % NT == 0 || idx < TOT) {
+#pragma unroll
+            for (int r = 0; r < R; r++) v[q][r] = buf[tile_addr<COLS, NB, RS>(jj[q] + r * BF, cc[q])];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        int idx = tid + q * NT;
+        if (TOT % NT == 0 || idx < TOT) {
+            const int j = jj[q];
+            const int k = (NS == 1) ? 0 : j % NS;
+            if (NS > 1 && k != 0) {
+#pragma unroll
+                for (int r = 1; r < R; r++) {
+                    uint32_t e = (uint32_t)(r * k) * ESTEP * tscale;
+                    v[q][r] = cmul(v[q][r], tw_get<INV>(tw, e));
+                }
+            }
+            dftR<R, INV>(v[q]);
+            const int out = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; r++) buf[tile_addr<COLS, NB, RS>(out + r * NS, cc[q])] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int P, int NS, int NB, int NT, bool INV, bool COLS, int RS>
+__device__ __forceinline__ void fft_stages(double2* buf, const Tw& tw, uint32_t tscale)
+{
+    if constexpr (NS < P) {
+        constexpr int R = pick_radix(P / NS);
+        fft_stage<P, R, NS, NB, NT, INV, COLS, RS>(buf, tw, tscale);
+        fft_stages<P, NS * R, NB, NT, INV, COLS, RS>(buf, tw, tscale);
+    }
+}
+
+// In-place DFT of NB sequences of length P in LDS.  tscale = M / P converts
+// exponents of exp(-2 pi i / P) into exponents of the table's root.
+// Caller must __syncthreads() before (data written) - the routine ends with
+// a barrier.
+template <int P, int NB, int NT, bool INV, bool COLS, int RS = P>
+__device__ __forceinline__ void tile_fft(double2* buf, const Tw& tw, uint32_t tscale)
+{
+    fft_stages<P, 1, NB, NT, INV, COLS, RS>(buf, tw, tscale);
+}
+
+}  // namespace tmul

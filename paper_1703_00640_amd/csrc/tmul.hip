@@ -1,0 +1,486 @@
+// C-ABI of the truncated-multiplication library (see include/tmul.h).
+// Host code: planning, twiddle cache, template dispatch, launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+#include "tmul.h"
+#include "plan.hpp"
+#include "kernels.hpp"
+
+using namespace tmul;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tm_status hip_fail(hipError_t e, const char* what)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    g_last_error = buf;
+    return TM_ERR_HIP;
+}
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+    } while (0)
+
+// ------------------------------------------------------------ twiddles
+
+struct TwEntry {
+    double2* buf = nullptr;
+    Tw tw{};
+};
+
+std::mutex g_tw_mu;
+std::map<std::pair<int, uint64_t>, TwEntry> g_tw;
+
+tm_status get_twiddles(uint64_t M, hipStream_t s, Tw& out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_tw_mu);
+    auto key = std::make_pair(dev, M);
+    auto it = g_tw.find(key);
+    if (it != g_tw.end()) {
+        out = it->second.tw;
+        return TM_OK;
+    }
+    uint32_t sh = (uint32_t)((lg_ceil(M) + 1) / 2);
+    uint32_t S = 1u << sh;
+    uint32_t nhi = (uint32_t)((M + S - 1) / S);
+    TwEntry e;
+    HIP_TRY(hipMalloc(&e.buf, (size_t)(S + nhi) * sizeof(double2)));
+    uint32_t n = S > nhi ? S : nhi;
+    hipLaunchKernelGGL(k_twiddles, dim3((n + 255) / 256), dim3(256), 0, s, e.buf, e.buf + S,
+                       (uint32_t)M, S, nhi);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    e.tw.lo = e.buf;
+    e.tw.hi = e.buf + S;
+    e.tw.shift = sh;
+    e.tw.mask = S - 1;
+    g_tw[key] = e;
+    out = e.tw;
+    return TM_OK;
+}
+
+// ------------------------------------------------------------ dispatch
+
+constexpr int w_for(int L1)
+{
+    int lim = TILE / L1 < 16 ? TILE / L1 : 16;
+    int w = 1;
+    while (w * 2 <= lim) w *= 2;
+    return w;
+}
+
+#define TM_L1_LIST(X) \
+    X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) \
+    X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048) X(3072) X(4096)
+
+template <int KIND>
+bool launch_k1(uint32_t L1, const KParams& p, hipStream_t s)
+{
+    switch (L1) {
+#define X(V) \
+    case V: hipLaunchKernelGGL((k1_split_map_col<V, w_for(V), KIND>), dim3(p.L2 / w_for(V), 2), dim3(NT), 0, s, p); return true;
+        TM_L1_LIST(X)
+#undef X
+    }
+    return false;
+}
+
+bool launch_k3(uint32_t L1, const KParams& p, hipStream_t s)
+{
+    switch (L1) {
+#define X(V) \
+    case V: hipLaunchKernelGGL((k3_col_inverse<V, w_for(V)>), dim3(p.L2 / w_for(V)), dim3(NT), 0, s, p); return true;
+        TM_L1_LIST(X)
+#undef X
+    }
+    return false;
+}
+
+bool launch_k2(uint32_t L2, const KParams& p, hipStream_t s)
+{
+    dim3 g(p.L1 / 2 + 1);
+    switch (L2) {
+    case 16: hipLaunchKernelGGL((k2_rows_pointwise<16>), g, dim3(NT), 0, s, p); return true;
+    case 32: hipLaunchKernelGGL((k2_rows_pointwise<32>), g, dim3(NT), 0, s, p); return true;
+    case 64: hipLaunchKernelGGL((k2_rows_pointwise<64>), g, dim3(NT), 0, s, p); return true;
+    case 128: hipLaunchKernelGGL((k2_rows_pointwise<128>), g, dim3(NT), 0, s, p); return true;
+    case 256: hipLaunchKernelGGL((k2_rows_pointwise<256>), g, dim3(NT), 0, s, p); return true;
+    case 512: hipLaunchKernelGGL((k2_rows_pointwise<512>), g, dim3(NT), 0, s, p); return true;
+    case 1024: hipLaunchKernelGGL((k2_rows_pointwise<1024>), g, dim3(NT), 0, s, p); return true;
+    }
+    return false;
+}
+
+template <bool DIAG>
+void launch_k4(int kind, const KParams& p, hipStream_t s)
+{
+    dim3 g(p.nstatus);
+    if (kind == TM_FULL) hipLaunchKernelGGL((k4_backmap_carry<K_FULL, DIAG>), g, dim3(NT), 0, s, p);
+    else if (kind == TM_LO) hipLaunchKernelGGL((k4_backmap_carry<K_LO, DIAG>), g, dim3(NT), 0, s, p);
+    else hipLaunchKernelGGL((k4_backmap_carry<K_HI, DIAG>), g, dim3(NT), 0, s, p);
+}
+
+bool launch_k1_any(int kind, const KParams& p, hipStream_t s)
+{
+    if (kind == TM_FULL) return launch_k1<K_FULL>(p.L1, p, s);
+    if (kind == TM_LO) return launch_k1<K_LO>(p.L1, p, s);
+    return launch_k1<K_HI>(p.L1, p, s);
+}
+
+// ------------------------------------------------------------ params
+
+double inv_fact(int r)
+{
+    double f = 1.0;
+    for (int i = 2; i <= r; i++) f *= i;
+    return 1.0 / f;
+}
+
+void fill_params(const Plan& P, const uint64_t* u, const uint64_t* v, uint64_t* w, void* ws,
+                 tm_guard* guard, const Tw& tw, KParams& p)
+{
+    memset(&p, 0, sizeof p);
+    char* base = static_cast<char*>(ws);
+    p.u = u;
+    p.v = v;
+    p.w = w;
+    p.n = P.n;
+    p.L = P.L;
+    p.b = P.b;
+    p.lam = P.lam;
+    p.N = (uint32_t)P.N;
+    p.digits = (uint32_t)P.digits;
+    p.M = (uint32_t)P.M;
+    p.L1 = P.L1;
+    p.L2 = P.L2;
+    p.jmax = P.jmax;
+    p.shift = P.shift;
+    p.off = P.off;
+    p.out_bits = P.out_bits;
+    p.out_limbs = P.out_limbs;
+    p.ncoef = (uint32_t)P.ncoef;
+    p.ncover = (uint32_t)P.ncover;
+    p.nstatus = P.nstatus;
+    p.invN = 1.0 / (double)P.N;
+    p.invM = 1.0 / (double)P.M;
+    const double eps = ldexp(1.0, -P.b);
+    for (int r = 0; r < LMAX; r++) {
+        double e = 1.0;
+        for (int i = 0; i < r; i++) e *= eps;
+        double s_alt = (r & 1) ? -1.0 : 1.0;   // (-eps)^r sign
+        // forward map: alpha (low) has (-eps)^r, gamma (high) eps^r
+        p.cf[r] = (P.kind == TM_LO ? s_alt : 1.0) * e * inv_fact(r);
+        // back map: beta (low) eps^r, delta (high) (-eps)^r
+        p.cb[r] = (P.kind == TM_LO ? 1.0 : s_alt) * e * inv_fact(r);
+    }
+    p.za = reinterpret_cast<double2*>(base + P.o_za);
+    p.zb = reinterpret_cast<double2*>(base + P.o_zb);
+    p.status = reinterpret_cast<uint64_t*>(base + P.o_status);
+    p.ticket = reinterpret_cast<uint32_t*>(base + P.o_ticket);
+    p.guard = guard ? guard : reinterpret_cast<tm_guard*>(base + P.o_guard);
+    p.tw = tw;
+}
+
+tm_status plan_for(tm_kind kind, uint64_t n, Plan& P, int bt = 0, int bf = 0)
+{
+    if (kind != TM_FULL && kind != TM_LO && kind != TM_HI) {
+        g_last_error = "invalid kind";
+        return TM_ERR_INVALID;
+    }
+    if (n == 0) {
+        g_last_error = "n_bits must be positive";
+        return TM_ERR_INVALID;
+    }
+    if (!bt) {
+        const char* e = getenv("TM_FORCE_B");
+        if (e && *e) bt = atoi(e);
+    }
+    if (!bf) {
+        const char* e = getenv("TM_FORCE_B_FULL");
+        if (e && *e) bf = atoi(e);
+    }
+    if (!make_plan((int)kind, n, bt, bf, P)) {
+        g_last_error = "unsupported size";
+        return TM_ERR_UNSUPPORTED;
+    }
+    return TM_OK;
+}
+
+enum Mode { RUN, DIAG_RUN };
+
+tm_status run(const Plan& P, uint64_t* w, const uint64_t* u, const uint64_t* v, void* ws,
+              size_t ws_bytes, hipStream_t s, tm_guard* guard, Mode mode, int64_t* dc,
+              double* dx, hipEvent_t* ev)
+{
+    if (!u || !v || !ws || (mode == RUN && !w) || (mode == DIAG_RUN && !dc)) {
+        g_last_error = "null pointer";
+        return TM_ERR_INVALID;
+    }
+    if (ws_bytes < P.ws_bytes) {
+        g_last_error = "workspace too small";
+        return TM_ERR_INVALID;
+    }
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) {
+        g_last_error = "workspace must be 256-byte aligned";
+        return TM_ERR_INVALID;
+    }
+    Tw tw;
+    tm_status st = get_twiddles(P.M, s, tw);
+    if (st != TM_OK) return st;
+    KParams p;
+    uint64_t dummy_out = 0;
+    (void)dummy_out;
+    fill_params(P, u, v, w, ws, guard, tw, p);
+    if (mode == DIAG_RUN) {
+        // K1 clears out_limbs of w; point it at the coefficient buffer's
+        // storage only when no output exists: use zero output limbs instead
+        p.w = reinterpret_cast<uint64_t*>(dc);
+        p.out_limbs = 0;
+        p.dbg_c = dc;
+        p.dbg_x = dx;
+    }
+    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    if (!launch_k1_any(P.kind, p, s)) {
+        g_last_error = "no kernel for L1";
+        return TM_ERR_UNSUPPORTED;
+    }
+    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+    if (!launch_k2(P.L2, p, s)) {
+        g_last_error = "no kernel for L2";
+        return TM_ERR_UNSUPPORTED;
+    }
+    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+    launch_k3(P.L1, p, s);
+    if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+    if (mode == DIAG_RUN) launch_k4<true>(P.kind, p, s);
+    else launch_k4<false>(P.kind, p, s);
+    if (ev) HIP_TRY(hipEventRecord(ev[4], s));
+    HIP_TRY(hipGetLastError());
+    return TM_OK;
+}
+
+// Fallback plan of tm_mul_checked: two bits smaller digits for the truncated
+// products, four bits smaller for the full product.
+bool fallback_plan(tm_kind kind, uint64_t n_bits, const Plan& P, Plan& F)
+{
+    int bt = P.kind == TM_FULL ? 0 : P.b - 2;
+    int bf = P.kind == TM_FULL ? P.b - 4 : 0;
+    return make_plan((int)kind, n_bits, bt, bf, F);
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+size_t tm_workspace_bytes(tm_kind kind, uint64_t n_bits)
+{
+    Plan P;
+    if (plan_for(kind, n_bits, P) != TM_OK) return 0;
+    return P.ws_bytes;
+}
+
+tm_status tm_plan_query(tm_kind kind, uint64_t n_bits, tm_plan_info* out)
+{
+    if (!out) {
+        g_last_error = "null pointer";
+        return TM_ERR_INVALID;
+    }
+    Plan P;
+    tm_status st = plan_for(kind, n_bits, P);
+    if (st != TM_OK) return st;
+    out->kind = (uint32_t)kind;
+    out->via_full = P.via_full ? 1u : 0u;
+    out->b = (uint32_t)P.b;
+    out->lambda = (uint32_t)P.lam;
+    out->n_bits = n_bits;
+    out->N = P.N;
+    out->digits = P.digits;
+    out->M = P.M;
+    out->L1 = P.L1;
+    out->L2 = P.L2;
+    out->workspace_bytes = P.ws_bytes;
+    return TM_OK;
+}
+
+tm_status tm_mul(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v,
+                 uint64_t n_bits, void* workspace, size_t workspace_bytes, hipStream_t stream,
+                 tm_guard* guard_dev)
+{
+    Plan P;
+    tm_status st = plan_for(kind, n_bits, P);
+    if (st != TM_OK) return st;
+    return run(P, w, u, v, workspace, workspace_bytes, stream, guard_dev, RUN, nullptr, nullptr,
+               nullptr);
+}
+
+tm_status tm_mul_full(uint64_t* w, const uint64_t* u, const uint64_t* v, uint64_t n_bits,
+                      void* workspace, size_t workspace_bytes, hipStream_t stream,
+                      tm_guard* guard_dev)
+{
+    return tm_mul(TM_FULL, w, u, v, n_bits, workspace, workspace_bytes, stream, guard_dev);
+}
+
+tm_status tm_mul_lo(uint64_t* w, const uint64_t* u, const uint64_t* v, uint64_t n_bits,
+                    void* workspace, size_t workspace_bytes, hipStream_t stream,
+                    tm_guard* guard_dev)
+{
+    return tm_mul(TM_LO, w, u, v, n_bits, workspace, workspace_bytes, stream, guard_dev);
+}
+
+tm_status tm_mul_hi(uint64_t* w, const uint64_t* u, const uint64_t* v, uint64_t n_bits,
+                    void* workspace, size_t workspace_bytes, hipStream_t stream,
+                    tm_guard* guard_dev)
+{
+    return tm_mul(TM_HI, w, u, v, n_bits, workspace, workspace_bytes, stream, guard_dev);
+}
+
+size_t tm_workspace_bytes_batched(const tm_request* reqs, size_t count)
+{
+    size_t m = 0;
+    if (!reqs) return 0;
+    for (size_t i = 0; i < count; i++) {
+        size_t b = tm_workspace_bytes((tm_kind)reqs[i].kind, reqs[i].n_bits);
+        if (b == 0) return 0;
+        if (b > m) m = b;
+    }
+    return m;
+}
+
+tm_status tm_mul_batched(const tm_request* reqs, size_t count, void* workspace,
+                         size_t workspace_bytes, hipStream_t stream, tm_guard* guards_dev)
+{
+    if (!reqs && count) {
+        g_last_error = "null pointer";
+        return TM_ERR_INVALID;
+    }
+    for (size_t i = 0; i < count; i++) {
+        tm_status st = tm_mul((tm_kind)reqs[i].kind, reqs[i].w, reqs[i].u, reqs[i].v,
+                              reqs[i].n_bits, workspace, workspace_bytes, stream,
+                              guards_dev ? guards_dev + i : nullptr);
+        if (st != TM_OK) return st;
+    }
+    return TM_OK;
+}
+
+size_t tm_workspace_bytes_checked(tm_kind kind, uint64_t n_bits)
+{
+    Plan P, F;
+    if (plan_for(kind, n_bits, P) != TM_OK) return 0;
+    size_t m = P.ws_bytes;
+    if (fallback_plan(kind, n_bits, P, F)) m = F.ws_bytes > m ? F.ws_bytes : m;
+    return m;
+}
+
+tm_status tm_mul_checked(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v,
+                         uint64_t n_bits, void* workspace, size_t workspace_bytes,
+                         hipStream_t stream, tm_guard* guard_host)
+{
+    Plan P;
+    tm_status st = plan_for(kind, n_bits, P);
+    if (st != TM_OK) return st;
+    tm_guard g;
+    for (int attempt = 0; attempt < 2; attempt++) {
+        st = run(P, w, u, v, workspace, workspace_bytes, stream, nullptr, RUN, nullptr, nullptr,
+                 nullptr);
+        if (st != TM_OK) return st;
+        HIP_TRY(hipMemcpyAsync(&g, static_cast<char*>(workspace) + P.o_guard, sizeof g,
+                               hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        if (guard_host) *guard_host = g;
+        if (g.flags == 0) return TM_OK;
+        if (attempt == 0) {
+            Plan F;
+            if (!fallback_plan(kind, n_bits, P, F)) break;
+            P = F;
+        }
+    }
+    g_last_error = "rounding guard tripped after fallback";
+    return TM_ERR_PRECISION;
+}
+
+tm_status tm_coefficients(tm_kind kind, int64_t* coeffs, double* x, uint64_t coeffs_len,
+                          const uint64_t* u, const uint64_t* v, uint64_t n_bits,
+                          void* workspace, size_t workspace_bytes, hipStream_t stream,
+                          tm_guard* guard_dev)
+{
+    Plan P;
+    tm_status st = plan_for(kind, n_bits, P);
+    if (st != TM_OK) return st;
+    if (coeffs_len < P.ncoef) {
+        g_last_error = "coefficient buffer too small";
+        return TM_ERR_INVALID;
+    }
+    return run(P, nullptr, u, v, workspace, workspace_bytes, stream, guard_dev, DIAG_RUN, coeffs,
+               x, nullptr);
+}
+
+tm_status tm_profile_stages(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v,
+                            uint64_t n_bits, void* workspace, size_t workspace_bytes,
+                            hipStream_t stream, float* stage_ms, const char** names, int cap,
+                            int* n_stages)
+{
+    static const char* kNames[4] = {"split_map_colfft", "rowfft_pointwise_rowifft",
+                                    "col_ifft", "backmap_round_carry"};
+    if (!stage_ms || !n_stages || cap < 4) {
+        g_last_error = "stage buffer too small";
+        return TM_ERR_INVALID;
+    }
+    Plan P;
+    tm_status st = plan_for(kind, n_bits, P);
+    if (st != TM_OK) return st;
+    hipEvent_t ev[5];
+    for (int i = 0; i < 5; i++) HIP_TRY(hipEventCreate(&ev[i]));
+    st = run(P, w, u, v, workspace, workspace_bytes, stream, nullptr, RUN, nullptr, nullptr, ev);
+    if (st == TM_OK) {
+        hipError_t e = hipEventSynchronize(ev[4]);
+        if (e != hipSuccess) st = hip_fail(e, "hipEventSynchronize");
+        for (int i = 0; st == TM_OK && i < 4; i++) {
+            e = hipEventElapsedTime(&stage_ms[i], ev[i], ev[i + 1]);
+            if (e != hipSuccess) st = hip_fail(e, "hipEventElapsedTime");
+            if (names) names[i] = kNames[i];
+        }
+        *n_stages = 4;
+    }
+    for (int i = 0; i < 5; i++) (void)hipEventDestroy(ev[i]);
+    return st;
+}
+
+const char* tm_status_string(tm_status s)
+{
+    switch (s) {
+    case TM_OK: return "ok";
+    case TM_ERR_INVALID: return "invalid argument";
+    case TM_ERR_HIP: return "HIP error";
+    case TM_ERR_PRECISION: return "rounding guard tripped";
+    case TM_ERR_UNSUPPORTED: return "unsupported size";
+    }
+    return "unknown status";
+}
+
+const char* tm_last_error(void) { return g_last_error.c_str(); }
+
+void tm_release_caches(void)
+{
+    std::lock_guard<std::mutex> lk(g_tw_mu);
+    for (auto& kv : g_tw) (void)hipFree(kv.second.buf);
+    g_tw.clear();
+}
+
+}  // extern "C"

@@ -1,0 +1,215 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI.
+
+Low and full products must equal the oracle bit for bit; high products must
+be one of the at most two allowed values AND equal the plan-exact value
+round(S / 2^D) with S from the exact closed-form coefficients (Prop.
+high-cancel).  Rounded coefficients are compared bit for bit with the closed
+forms; the unrounded ones with the FP64 model within a stated tolerance.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import method as m
+from paper_1703_00640_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _tm():
+    import paper_1703_00640_amd as tm
+    return tm
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to(dev())
+
+
+def to_host(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_kind(kind, u, v, n, guard=True):
+    tm = _tm()
+    g = tm.new_guard(dev()) if guard else None
+    out = tm.mul(kind, to_dev(u), to_dev(v), n, guard=g)
+    torch.cuda.synchronize()
+    return to_host(out), (tm.read_guard(g) if guard else None)
+
+
+def check_all(u, v, n, threads=8, expect_guard_ok=True):
+    lo, glo = run_kind("lo", u, v, n)
+    hi, ghi = run_kind("hi", u, v, n)
+    full, gfu = run_kind("full", u, v, n)
+    want_full = oracle.mul_full(u, v, n, threads)
+    assert np.array_equal(full, want_full), "full product mismatch n=%d" % n
+    assert np.array_equal(lo, oracle.mul_lo(u, v, n, threads)), "low product mismatch n=%d" % n
+    q, nz = oracle.mul_hi(u, v, n, threads)
+    assert oracle.hi_accepts(hi, q, nz), "high product not in allowed set n=%d" % n
+    if expect_guard_ok:
+        for g in (glo, ghi, gfu):
+            assert g.flags == 0 and g.max_dist < 0.25, g.as_dict()
+    return glo, ghi, gfu
+
+
+RAGGED = [1, 2, 7, 63, 64, 65, 100, 640, 1000, 1024, 1025, 1100, 2047, 2048, 2049,
+          3000, 4096, 5000, 8191, 12345, 30000, 65536, 65537, 100000, 262144 + 77]
+
+
+@pytest.mark.parametrize("n", RAGGED)
+def test_random_parity_ragged(n):
+    say("[parity] n=%d" % n)
+    u, v = inputs.operand_pair(n, 100 + n % 97)
+    check_all(u, v, n)
+
+
+def test_config_small_n65536_with_edges():
+    """n = 2^16: random operands plus all-ones, (2^n - 1) x 1, powers of two
+    and zero."""
+    n = 1 << 16
+    say("[parity] n=2^16 random + edges")
+    u, v = inputs.operand_pair(n, 1)
+    glo, ghi, gfu = check_all(u, v, n)
+    say("  guard lo %.3g hi %.3g full %.3g" % (glo.max_dist, ghi.max_dist, gfu.max_dist))
+    ones, one = inputs.all_ones(n), inputs.small(n, 1)
+    zero = np.zeros_like(ones)
+    for a, b_ in ((ones, ones), (ones, one), (one, ones), (zero, ones),
+                  (inputs.power_of_two(n, n - 1), inputs.power_of_two(n, n - 1)),
+                  (inputs.power_of_two(n, 12345), inputs.power_of_two(n, 777))):
+        check_all(a, b_, n)
+
+
+def test_adversarial_digits_small():
+    """Every digit at the edge of its balanced range (Section 5 warns that
+    such inputs grow the coefficients); at n = 2^16 the plan still holds."""
+    n = 1 << 16
+    tm = _tm()
+    for kind in ("lo", "hi"):
+        pl = tm.plan(kind, n)
+        shift = pl["N"] * pl["b"] + pl["b"] - n if kind == "hi" else 0
+        a = inputs.digit_pattern(n, pl["b"], 1 << (pl["b"] - 1), shift)
+        check_all(a, a, n)
+
+
+@pytest.mark.parametrize("n", [4096, 1 << 16, 100003])
+def test_rounded_coefficients_bit_exact(n):
+    """c_i = round(2^b W-bar_i) equals 2^b L_i (Prop. low-cancel) and
+    2^b H_i (Prop. high-cancel) exactly; full: c_i = w_i."""
+    tm = _tm()
+    u, v = inputs.operand_pair(n, 7)
+    ui, vi = oracle.to_int(u), oracle.to_int(v)
+    for kind in ("lo", "hi", "full"):
+        say("[coeffs] n=%d %s" % (n, kind))
+        pl = tm.plan(kind, n)
+        c, x, g = tm.coefficients(kind, to_dev(u), to_dev(v), n)
+        c = c.cpu().numpy()
+        N, b = pl["N"], pl["b"]
+        if kind == "lo":
+            U = m.balanced_digits(m.unsigned_digits(ui, N, b), b, False)
+            V = m.balanced_digits(m.unsigned_digits(vi, N, b), b, False)
+            want = m.low_coeffs_exact([int(t) for t in m.digit_product(U, V)], N, b)
+        elif kind == "hi":
+            s = (N + 1) * b - n
+            U = m.balanced_digits(m.unsigned_digits(ui, N + 1, b, s), b, True)
+            V = m.balanced_digits(m.unsigned_digits(vi, N + 1, b, s), b, True)
+            want = m.high_coeffs_exact([int(t) for t in m.digit_product(U, V)], N, b)
+            # plan-exact high product: round(S / 2^D)
+            D = (N + 3) * b - n
+            S = m.overlap_add(want, b)
+            w_exact = (S + (1 << (D - 1))) >> D
+            hi, _ = run_kind("hi", u, v, n, guard=False)
+            assert oracle.to_int(hi) == w_exact
+        else:
+            nd = pl["digits"]
+            U = m.balanced_digits(m.unsigned_digits(ui, nd, b), b, True)
+            V = m.balanced_digits(m.unsigned_digits(vi, nd, b), b, True)
+            W = [int(t) for t in m.digit_product(U, V)]
+            want = W + [0] * (N - len(W))
+        assert [int(t) for t in c] == [int(t) for t in want], kind
+        assert g.flags == 0 and g.max_dist < 0.25
+
+
+def test_unrounded_values_match_fp64_model():
+    """x_i from the GPU against the oracle's FP64 model of the algorithms
+    (same digits, maps, lambda, N): both approximate the same integers; the
+    difference is bounded by the two rounding-error budgets.  Tolerance:
+    0.05 absolute (each side's max distance to the integers is < 0.02 here)."""
+    tm = _tm()
+    n = 1 << 14
+    u, v = inputs.operand_pair(n, 9)
+    ui, vi = oracle.to_int(u), oracle.to_int(v)
+    for kind in ("lo", "hi", "full"):
+        pl = tm.plan(kind, n)
+        c, x, g = tm.coefficients(kind, to_dev(u), to_dev(v), n)
+        x = x.cpu().numpy()
+        if kind == "lo":
+            r = m.low_product(ui, vi, n, pl["b"], pl["N"], pl["lam"])
+        elif kind == "hi":
+            r = m.high_product(ui, vi, n, pl["b"], pl["N"], pl["lam"])
+        else:
+            r = m.full_product(ui, vi, n, pl["b"], pl["digits"])
+        assert np.max(np.abs(x - r["x"][:len(x)])) < 0.05, kind
+
+
+def test_determinism_and_guard_reported():
+    n = 1 << 18
+    u, v = inputs.operand_pair(n, 11)
+    for kind in ("lo", "hi", "full"):
+        a, g1 = run_kind(kind, u, v, n)
+        b_, g2 = run_kind(kind, u, v, n)
+        assert np.array_equal(a, b_)
+        assert g1.max_dist == g2.max_dist and g1.max_dist < 0.25
+
+
+def test_config_n2_24_parity():
+    """n = 2^24, one multiplication at a time: lo, hi, full vs the oracle."""
+    n = 1 << 24
+    say("[parity] n=2^24")
+    u, v = inputs.operand_pair(n, 2)
+    glo, ghi, gfu = check_all(u, v, n, threads=16)
+    say("  guard lo %.4g hi %.4g full %.4g" % (glo.max_dist, ghi.max_dist, gfu.max_dist))
+
+
+def test_b16_truncated_trips_guard_and_checked_recovers(monkeypatch):
+    """Negative control: the configs' literal b = 16 for the truncated
+    product exceeds the FP64 budget (3b + lg N > 53); the guard must trip,
+    and the checked entry point must fall back and return the right value."""
+    tm = _tm()
+    n = 1 << 16
+    u, v = inputs.operand_pair(n, 3)
+    monkeypatch.setenv("TM_FORCE_B", "16")
+    lo, g = run_kind("lo", u, v, n)
+    say("  b=16 low product guard:", g.as_dict())
+    assert g.b == 16 and g.flags != 0
+    out, g2 = tm.mul_checked("lo", to_dev(u), to_dev(v), n)
+    assert g2.flags == 0 and g2.b == 14
+    assert np.array_equal(to_host(out), oracle.mul_lo(u, v, n))
+
+
+def test_batched_matches_single():
+    tm = _tm()
+    reqs, want = [], []
+    for i, (kind, n) in enumerate([("lo", 5000), ("hi", 70000), ("full", 3000), ("lo", 64),
+                                   ("hi", 1 << 16), ("full", 100)]):
+        u, v = inputs.operand_pair(n, 50 + i)
+        L = (n + 63) // 64
+        out = torch.zeros(2 * L if kind == "full" else L, dtype=torch.int64, device=dev())
+        reqs.append((kind, to_dev(u), to_dev(v), n, out))
+        want.append(run_kind(kind, u, v, n, guard=False)[0])
+    tm.mul_batched(reqs)
+    torch.cuda.synchronize()
+    for r, w in zip(reqs, want):
+        assert np.array_equal(to_host(r[4]), w)

@@ -1,0 +1,92 @@
+"""Host-side checks of the HIP library (no GPU needed): it loads, exports
+every entry point declared in include/tmul.h, plans every benchmark size
+within the theorems' constraints, and rejects bad arguments before touching
+the device."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tmul.h")
+LIB = os.path.join(ROOT, "paper_1703_00640_amd", "libtmul.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libtmul.so not built")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for must in ("tm_mul", "tm_mul_lo", "tm_mul_hi", "tm_mul_full", "tm_mul_batched",
+                 "tm_workspace_bytes", "tm_plan_query", "tm_mul_checked"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def _plan(kind, n):
+    import paper_1703_00640_amd as tm
+    return tm.plan(kind, n)
+
+
+def lg(x):
+    return (x - 1).bit_length()
+
+
+@pytest.mark.parametrize("n", [1 << 16, 1 << 24, 1 << 26, 12345, 2049, 1000003])
+def test_plans_satisfy_theorem_constraints(n):
+    lo, hi, full = _plan("lo", n), _plan("hi", n), _plan("full", n)
+    # low product: b >= 4, N >= 3, N b >= n (Theorem on the low product)
+    assert lo["b"] >= 4 and lo["N"] >= 3 and lo["N"] * lo["b"] >= n
+    # high product: (N + 1) b >= n + lg N + 2 (Theorem on the high product)
+    assert hi["N"] * hi["b"] + hi["b"] >= n + lg(hi["N"]) + 2
+    # full product: N digits with N b >= n, length 2N
+    assert full["digits"] * full["b"] >= n and full["N"] == 2 * full["digits"]
+    for p in (lo, hi, full):
+        assert p["M"] * 2 == p["N"] and p["L1"] * p["L2"] == p["M"]
+        odd = p["N"]
+        while odd % 2 == 0:
+            odd //= 2
+        assert odd in (1, 3)
+
+
+def test_config_plans():
+    """n = 2^24: truncated b = 11 at N = 3 * 2^19, full b = 16 at 2N = 2^21
+    (transform length ratio 0.75)."""
+    lo, full = _plan("lo", 1 << 24), _plan("full", 1 << 24)
+    assert (lo["b"], lo["N"]) == (11, 3 << 19)
+    assert (full["b"], full["N"]) == (16, 1 << 21)
+    assert lo["N"] / full["N"] == 0.75
+    assert 5 <= lo["lam"] <= 7
+
+
+def test_small_n_routes_to_full():
+    for n in (1, 64, 1000):
+        assert _plan("lo", n)["via_full"] == 1
+        assert _plan("hi", n)["via_full"] == 1
+    assert _plan("lo", 4096)["via_full"] == 0
+
+
+def test_invalid_arguments_rejected_without_gpu():
+    import paper_1703_00640_amd as tm
+    lib = tm._load()
+    ws = tm.workspace_bytes("lo", 4096)
+    # null operands
+    assert lib.tm_mul(1, None, None, None, 4096, None, ws, None, None) == 1
+    # bad kind, n = 0
+    assert lib.tm_workspace_bytes(7, 4096) == 0
+    assert lib.tm_workspace_bytes(1, 0) == 0
+    info = tm._PlanInfo()
+    assert lib.tm_plan_query(1, 0, ctypes.byref(info)) == 1
+    assert lib.tm_status_string(3) == b"rounding guard tripped"
