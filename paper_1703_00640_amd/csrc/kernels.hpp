@@ -29,9 +29,11 @@ enum { K_FULL = 0, K_LO = 1, K_HI = 2 };
 constexpr int NT = 256;         // threads per workgroup, every kernel
 constexpr int LMAX = 9;         // largest supported series length lambda
 constexpr int DPT = 7;          // digits per thread in K4
-constexpr int DPW = DPT * NT;   // digits per workgroup in K4
+constexpr int NT4 = 1024;       // threads per K4 workgroup
+constexpr int DPW = DPT * NT4;  // digits per workgroup in K4
 constexpr int TILE = 4096;      // complex elements per column tile (64 KiB)
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
+constexpr int K4_HALO = 32;        // q values staged below a K4 workgroup's range
 
 struct KParams {
     const uint64_t* u;
@@ -58,9 +60,10 @@ struct KParams {
     double cb[LMAX];    // same for the back map
     double2* za;        // operand u spectrum / convolution result
     double2* zb;        // operand v spectrum
-    uint64_t* status;   // K4 look-back records, 4 words each
+    uint64_t* status;   // K4 look-back records, 2 words each
     uint32_t* ticket;   // K4 dynamic workgroup counter
     tm_guard* guard;
+    double* theta;      // high product: theta_U, theta_V (written by K1)
     Tw tw;
     int64_t* dbg_c;     // diagnostic outputs (tm_coefficients) or null
     double* dbg_x;
@@ -145,54 +148,12 @@ __device__ __forceinline__ double hi_theta(const KParams& p, const uint64_t* x)
     return t;
 }
 
-// G_j and G_(j+1) of the sequence fed to the convolution:
-//   full: the digits themselves (zero beyond the digit count);
-//   low:  G = alpha* U   (Prop. approximating alpha*), cyclic indices;
-//   high: G = gamma* F'  with F'_k = F_k + 2^(-kb) F_N  (F mod C by eq.
-//         reduction-modC with rho ~ 2^b, Prop. approximating gamma-dagger).
-template <int KIND>
-__device__ __forceinline__ void gen_pair(const KParams& p, const uint64_t* x, uint32_t j,
-                                         double FN, double& g0, double& g1)
-{
-    if constexpr (KIND == K_FULL) {
-        g0 = j < p.digits ? (double)bal_digit(p, x, j, p.digits, true) : 0.0;
-        g1 = j + 1 < p.digits ? (double)bal_digit(p, x, j + 1, p.digits, true) : 0.0;
-    } else {
-        const uint32_t N = p.N;
-        const int lam = p.lam;
-        // d[t] = F'_(k) with k = (j + 1 - lam + t) mod N, t = 0..lam
-        double d[LMAX + 1];
-#pragma unroll
-        for (int t = 0; t <= LMAX; t++) {
-            if (t <= lam) {
-                uint32_t k = (uint32_t)(((int64_t)j + 1 - lam + t + (int64_t)N) % N);
-                double f = (double)bal_digit(p, x, k, p.digits, KIND == K_HI);
-                if (KIND == K_HI && k < p.jmax) f += ldexp(FN, -(int)k * p.b);
-                d[t] = f;
-            }
-        }
-        double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-        for (int r = LMAX - 1; r >= 0; r--) {
-            if (r < lam) {
-                // G_j gets F'_(j-r) = d[lam-1-r]; G_(j+1) gets F'_(j+1-r) = d[lam-r]
-                uint32_t k0 = (uint32_t)(((int64_t)j - r + (int64_t)N) % N);
-                uint32_t k1 = (uint32_t)(((int64_t)j + 1 - r + (int64_t)N) % N);
-                s0 = fma(coef_fwd(KIND, k0, r, p.invN, p.cf[r]), d[lam - 1 - r], s0);
-                s1 = fma(coef_fwd(KIND, k1, r, p.invN, p.cf[r]), d[lam - r], s1);
-            }
-        }
-        g0 = s0;
-        g1 = s1;
-    }
-}
-
 // Clear the per-call state that K4 accumulates into (output limbs for the
 // partial-limb OR, guard, look-back records, ticket).  Done by K1.
 __device__ __forceinline__ void clear_state(const KParams& p, uint32_t gid, uint32_t gsize)
 {
     for (uint64_t i = gid; i < p.out_limbs; i += gsize) p.w[i] = 0;
-    for (uint64_t i = gid; i < 4ull * p.nstatus; i += gsize) p.status[i] = 0;
+    for (uint64_t i = gid; i < 2ull * p.nstatus; i += gsize) p.status[i] = 0;
     if (gid == 0) {
         *p.ticket = 0;
         tm_guard g;
@@ -209,33 +170,102 @@ __device__ __forceinline__ void clear_state(const KParams& p, uint32_t gid, uint
 
 // ------------------------------------------------------------------- K1
 
+// K1 tile area in double2 units: the tile, or the staged digits of the
+// truncated products (int16, row stride 2W + LMAX - 1), whichever is larger.
+constexpr int k1_nd(int W) { return 2 * W + LMAX - 1; }
+constexpr int k1_area(int L1, int W, int KIND)
+{
+    return KIND == K_FULL || L1 * W * 16 >= L1 * k1_nd(W) * 2 ? L1 * W : (L1 * k1_nd(W) * 2 + 15) / 16;
+}
+constexpr bool k1_fits(int L1, int W, int KIND) { return k1_area(L1, W, KIND) * 16 <= 65536; }
+
 template <int L1, int W, int KIND>
 __global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
 {
     static_assert(L1 * W <= TILE, "tile too large");
-    __shared__ double2 tile[L1 * W];
+    static_assert(k1_fits(L1, W, KIND), "K1 LDS area too large");
+    // ND digits per tile row: the row's 2W reals need digits
+    // [2 m0 - lam + 1, 2 m0 + 2W) (mod N); they are extracted once into the
+    // tile area (int16: truncated digits have at most 15 bits) before the
+    // map is evaluated.
+    constexpr int ND = k1_nd(W);
+    constexpr int PER = (L1 * W + NT - 1) / NT;
+    __shared__ double2 tile[k1_area(L1, W, KIND)];
     __shared__ double s_FN;
     const int op = blockIdx.y;
     const uint64_t* x = op ? p.v : p.u;
     double2* dst = op ? p.zb : p.za;
     const uint32_t L2 = p.L2;
     const uint32_t c0 = blockIdx.x * W;
+    const int tid = threadIdx.x;
 
-    if (op == 0) clear_state(p, blockIdx.x * NT + threadIdx.x, gridDim.x * NT);
-    if (KIND == K_HI && threadIdx.x == 0) s_FN = (double)bal_digit(p, x, p.N, p.digits, true);
-    __syncthreads();
-    const double FN = KIND == K_HI ? s_FN : 0.0;
+    if (op == 0) clear_state(p, blockIdx.x * NT + tid, gridDim.x * NT);
 
-    for (int e = threadIdx.x; e < L1 * W; e += NT) {
-        const int c = e % W, j1 = e / W;
-        const uint32_t m = (uint32_t)j1 * L2 + c0 + c;
-        double g0, g1;
-        gen_pair<KIND>(p, x, 2 * m, FN, g0, g1);
-        tile[e] = make_double2(g0, g1);
+    if constexpr (KIND == K_FULL) {
+        for (int e = tid; e < L1 * W; e += NT) {
+            const int c = e % W, j1 = e / W;
+            const uint32_t j = 2 * ((uint32_t)j1 * L2 + c0 + c);
+            const double g0 = j < p.digits ? (double)bal_digit(p, x, j, p.digits, true) : 0.0;
+            const double g1 = j + 1 < p.digits ? (double)bal_digit(p, x, j + 1, p.digits, true) : 0.0;
+            tile[e] = make_double2(g0, g1);
+        }
+        __syncthreads();
+    } else {
+        const uint32_t N = p.N;
+        const int lam = p.lam;
+        int16_t* dg = reinterpret_cast<int16_t*>(tile);
+        if (KIND == K_HI && tid == 0) {
+            s_FN = (double)bal_digit(p, x, N, p.digits, true);
+            if (blockIdx.x == 0) p.theta[op] = hi_theta(p, x);
+        }
+        // phase A: digits, row-major [j1][t], t = 0 .. 2W + lam - 2
+        const int nd = 2 * W + lam - 1;
+        for (int e = tid; e < L1 * ND; e += NT) {
+            const int j1 = e / ND, t = e % ND;
+            if (t >= nd) continue;
+            const int64_t k0 = 2 * ((int64_t)j1 * L2 + c0) - lam + 1 + t;  // > -N, < N
+            const uint32_t k = (uint32_t)(k0 < 0 ? k0 + (int64_t)N : k0);
+            dg[j1 * ND + t] = (int16_t)bal_digit(p, x, k, p.digits, KIND == K_HI);
+        }
+        __syncthreads();
+        const double FN = KIND == K_HI ? s_FN : 0.0;
+        // phase B: G_j = sum_{r<lam} coef_{(j-r) mod N, r} F'_((j-r) mod N)
+        double2 gv[PER];
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int e = tid + q * NT;
+            if (L1 * W % NT == 0 || e < L1 * W) {
+                const int c = e % W, j1 = e / W;
+                const uint32_t j = 2 * ((uint32_t)j1 * L2 + c0 + c);
+                const int16_t* row = dg + j1 * ND + 2 * c;  // row[t] = F at j + 1 - lam + t
+                double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                for (int r = 0; r < LMAX; r++) {
+                    if (r < lam) {
+                        const uint32_t k0 = j >= (uint32_t)r ? j - r : j + N - r;
+                        const uint32_t k1 = j + 1 >= (uint32_t)r ? j + 1 - r : j + 1 + N - r;
+                        double f0 = (double)row[lam - 1 - r], f1 = (double)row[lam - r];
+                        if (KIND == K_HI) {
+                            if (k0 < p.jmax) f0 += ldexp(FN, -(int)k0 * p.b);
+                            if (k1 < p.jmax) f1 += ldexp(FN, -(int)k1 * p.b);
+                        }
+                        s0 = fma(coef_fwd(KIND, k0, r, p.invN, p.cf[r]), f0, s0);
+                        s1 = fma(coef_fwd(KIND, k1, r, p.invN, p.cf[r]), f1, s1);
+                    }
+                }
+                gv[q] = make_double2(s0, s1);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int e = tid + q * NT;
+            if (L1 * W % NT == 0 || e < L1 * W) tile[e] = gv[q];
+        }
+        __syncthreads();
     }
-    __syncthreads();
     tile_fft<L1, W, NT, false, true>(tile, p.tw, p.M / L1);
-    for (int e = threadIdx.x; e < L1 * W; e += NT) {
+    for (int e = tid; e < L1 * W; e += NT) {
         const int c = e % W, k1 = e / W;
         const uint32_t col = c0 + c;
         double2 val = tile[e];
@@ -362,14 +392,11 @@ __device__ __forceinline__ CarryF compose(CarryF f, CarryF g)
 
 __device__ __forceinline__ int64_t apply(CarryF f, int64_t c) { return f.A + (c >= f.T ? 1 : 0); }
 
-__device__ __forceinline__ uint64_t ld_acq(uint64_t* a)
-{
-    return __hip_atomic_load(a, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_rel(uint64_t* a, uint64_t v)
-{
-    __hip_atomic_store(a, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
+// Look-back records are 64-bit words holding a 2-bit state (0 empty,
+// 1 aggregate, 2 inclusive) and a 62-bit two's-complement value.  Each word
+// is written once per state by a single relaxed device-scope atomic store
+// and polled with relaxed device-scope atomic loads: no acquire/release
+// fences, which on this GPU would write back or invalidate the whole L2.
 __device__ __forceinline__ uint64_t ld_rlx(uint64_t* a)
 {
     return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -378,6 +405,27 @@ __device__ __forceinline__ void st_rlx(uint64_t* a, uint64_t v)
 {
     __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+constexpr int64_t V62_MAX = (1ll << 61) - 1, V62_MIN = -(1ll << 61);
+__device__ __forceinline__ uint64_t pack62(uint64_t state, int64_t v)
+{
+    v = v > V62_MAX ? V62_MAX : v < V62_MIN ? V62_MIN : v;
+    return (state << 62) | ((uint64_t)v & ((1ull << 62) - 1));
+}
+__device__ __forceinline__ int64_t unpack62(uint64_t w) { return (int64_t)(w << 2) >> 2; }
+// poll a record word until its state is non-zero (bounded)
+__device__ __forceinline__ uint64_t poll_word(uint64_t* a, bool& timed_out)
+{
+    uint64_t w;
+    uint32_t spins = 0;
+    while (((w = ld_rlx(a)) >> 62) == 0) {
+        if (++spins > SPIN_LIMIT) {
+            timed_out = true;
+            return w;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return w;
+}
 
 __device__ __forceinline__ double wave_max(double v)
 {
@@ -385,76 +433,74 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// x_i: the value rounded to c_i (see tm_guard)
+// x_i, the value rounded to c_i (see tm_guard), from the LDS copy of q
+// (sq[o + K4_HALO] = q at index base + o, cyclically: workgroup 0 holds the
+// top of q below its range):
 //   full: W_i                                       (Alg. full, step 4)
-//   low:  2^b W-bar_i with W-bar = beta* W (mod A)  (Prop. approximating
-//         beta*; X^(N+s) = X^s - 2^-b X^(s+1) for the wrapped terms)
-//   high: 2^b J_i, J = (1 - 2^-b X) H + psi C(X), H = delta* W (mod C),
-//         psi ~ theta_W, C_j ~ -2^(-jb)  (eq. crt-sum, Remark on Newton)
-template <int KIND>
-__device__ __forceinline__ double x_value(const KParams& p, const double* q, uint32_t i, double thW)
+//   low:  2^b W-bar_i, W-bar = beta* W mod A        (Prop. approximating
+//         beta*): sum_r beta_{i-r,r} W_(i-r) with cyclic indices, minus
+//         2^-b sum_{r>=i} beta_{N+i-1-r,r} W_(N+i-1-r) for 1 <= i < lam
+//         (X^(N+s) = X^s - 2^-b X^(s+1) mod A)
+//   high: 2^b J_i, J = (1 - 2^-b X) H + psi C(X), H = delta* W mod C,
+//         psi ~ theta_W, C_j ~ -2^(-jb)  (eq. crt-sum, Remark on Newton):
+//         H_i = sum_r delta_{i-r,r} W_(i-r) (r <= i) + sum_j 2^(-jb)
+//         sum_{r > i-j} delta_{N+i-j-r,r} W_(N+i-j-r)  (X^(N+s) = sum_j
+//         2^(-jb) X^(s+j) mod C)
+// The sums use the unnormalised q = M W.
+__device__ __forceinline__ double back_lo(const KParams& p, const double* sq, uint64_t base, uint32_t i)
 {
     const uint32_t N = p.N;
-    const int lam = p.lam, b = p.b;
-    if constexpr (KIND == K_FULL) {
-        return q[i] * p.invM;
-    } else if constexpr (KIND == K_LO) {
-        double s = 0.0;
-        for (int r = 0; r < lam; r++) {
-            if ((uint32_t)r <= i) s = fma(coef_back(K_LO, i - r, r, p.invN, p.cb[r]), q[i - r], s);
-            else s = fma(coef_back(K_LO, N + i - r, r, p.invN, p.cb[r]), q[N + i - r], s);
-        }
-        if (i >= 1 && i < (uint32_t)lam) {
-            double t = 0.0;
-            for (int r = (int)i; r < lam; r++)
-                t = fma(coef_back(K_LO, N + i - 1 - r, r, p.invN, p.cb[r]), q[N + i - 1 - r], t);
-            s = fma(-ldexp(1.0, -b), t, s);
-        }
-        return ldexp(s * p.invM, b);
-    } else {
-        // H_i for i < N (H on the unnormalised q)
-        auto H = [&](uint32_t ii) -> double {
-            double s = 0.0;
-            for (int r = 0; r < lam && (uint32_t)r <= ii; r++)
-                s = fma(coef_back(K_HI, ii - r, r, p.invN, p.cb[r]), q[ii - r], s);
-            if (ii < (uint32_t)lam + p.jmax) {
-                // X^(N+s') = sum_j 2^(-jb) X^(s'+j) mod C: target ii = s' + j
-                for (int j = 0; j <= (int)ii && j <= (int)p.jmax; j++) {
-                    double t = 0.0;
-                    for (int r = (int)ii - j + 1; r < lam; r++)
-                        t = fma(coef_back(K_HI, N + ii - j - r, r, p.invN, p.cb[r]), q[N + ii - j - r], t);
-                    s = fma(ldexp(1.0, -j * b), t, s);
-                }
-            }
-            return s;
-        };
-        const double eps = ldexp(1.0, -b);
-        double J;
-        if (i < N) {
-            double h = H(i);
-            double hm = i ? H(i - 1) : 0.0;
-            J = fma(-eps, hm, h) * p.invM - ldexp(thW, -(int)i * b);
-        } else {
-            J = -eps * H(N - 1) * p.invM + thW;
-        }
-        return ldexp(J, b);
+    const int o = (int)((int64_t)i - (int64_t)base) + K4_HALO;
+    double s = 0.0;
+    for (int r = 0; r < p.lam; r++) {
+        const uint32_t k = i >= (uint32_t)r ? i - r : i + N - r;
+        s = fma(coef_back(K_LO, k, r, p.invN, p.cb[r]), sq[o - r], s);
     }
+    if (i >= 1 && i < (uint32_t)p.lam) {
+        double t = 0.0;
+        for (int r = (int)i; r < p.lam; r++)
+            t = fma(coef_back(K_LO, N + i - 1 - r, r, p.invN, p.cb[r]), sq[o - 1 - r], t);
+        s = fma(-ldexp(1.0, -p.b), t, s);
+    }
+    return s;
+}
+
+__device__ __forceinline__ double back_hi(const KParams& p, const double* sq, uint64_t base, uint32_t i)
+{
+    const uint32_t N = p.N;
+    const int o = (int)((int64_t)i - (int64_t)base) + K4_HALO;
+    double s = 0.0;
+    for (int r = 0; r < p.lam && (uint32_t)r <= i; r++)
+        s = fma(coef_back(K_HI, i - r, r, p.invN, p.cb[r]), sq[o - r], s);
+    if (i < (uint32_t)p.lam + p.jmax) {
+        for (int j = 0; j <= (int)i && j <= (int)p.jmax; j++) {
+            double t = 0.0;
+            for (int r = (int)i - j + 1; r < p.lam; r++)
+                t = fma(coef_back(K_HI, N + i - j - r, r, p.invN, p.cb[r]), sq[o - j - r], t);
+            s = fma(ldexp(1.0, -j * p.b), t, s);
+        }
+    }
+    return s;
 }
 
 template <int KIND, bool DIAG>
-__global__ __launch_bounds__(NT) void k4_backmap_carry(KParams p)
+__global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
 {
+    constexpr int NW = NT4 / 64;
     __shared__ uint32_t s_g;
     __shared__ int64_t s_cin;
     __shared__ double s_thW;
-    __shared__ int64_t sA[NT], sT[NT];
-    __shared__ uint16_t sd[DPW];
-    const int tid = threadIdx.x;
+    __shared__ double sq[DPW + K4_HALO];
+    __shared__ int64_t sWA[NW], sWT[NW];
+    __shared__ double sGD[NW], sGA[NW];
+    __shared__ uint32_t sGF;
+    uint16_t* sd = reinterpret_cast<uint16_t*>(sq);  // digits reuse the q staging area
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const double* q = reinterpret_cast<const double*>(p.za);
 
     if (tid == 0) {
         s_g = DIAG ? blockIdx.x : atomicAdd(p.ticket, 1u);
-        if (KIND == K_HI) s_thW = hi_theta(p, p.u) * hi_theta(p, p.v);
+        if (KIND == K_HI) s_thW = p.theta[0] * p.theta[1];
     }
     __syncthreads();
     const uint32_t g = s_g;
@@ -463,7 +509,44 @@ __global__ __launch_bounds__(NT) void k4_backmap_carry(KParams p)
     const uint64_t i0 = base + (uint64_t)tid * DPT;
     const int b = p.b;
 
-    // rounded coefficients and guard
+    // stage q[base - HALO, base + DPW) (zero outside [0, N))
+    if (tid == 0) sGF = 0;
+    for (int e = tid; e < DPW + K4_HALO; e += NT4) {
+        int64_t i = (int64_t)base - K4_HALO + e;
+        if (i < 0 && KIND != K_FULL) i += p.N;  // cyclic: wrapped terms of the maps
+        sq[e] = (i >= 0 && i < (int64_t)p.N) ? q[i] : 0.0;
+    }
+    __syncthreads();
+
+    // x_i (see back_lo / back_hi) and rounded coefficients, with the guard
+    double xv[DPT];
+    if constexpr (KIND == K_FULL) {
+#pragma unroll
+        for (int t = 0; t < DPT; t++) xv[t] = sq[tid * DPT + t + K4_HALO] * p.invM;
+    } else if constexpr (KIND == K_LO) {
+#pragma unroll
+        for (int t = 0; t < DPT; t++) {
+            const uint64_t i = i0 + t;
+            xv[t] = i < p.ncoef ? ldexp(back_lo(p, sq, base, (uint32_t)i) * p.invM, b) : 0.0;
+        }
+    } else {
+        // H for i0-1 .. i0+DPT-1, then J_i = (H_i - 2^-b H_(i-1)) / M - theta_W 2^(-ib)
+        const double eps = ldexp(1.0, -b);
+        double hprev = (i0 >= 1 && i0 - 1 < p.N) ? back_hi(p, sq, base, (uint32_t)(i0 - 1)) : 0.0;
+#pragma unroll
+        for (int t = 0; t < DPT; t++) {
+            const uint64_t i = i0 + t;
+            if (i >= p.ncoef) { xv[t] = 0.0; continue; }
+            if (i < p.N) {
+                const double h = back_hi(p, sq, base, (uint32_t)i);
+                xv[t] = ldexp(fma(-eps, hprev, h) * p.invM - ldexp(thW, -(int)i * b), b);
+                hprev = h;
+            } else {
+                xv[t] = ldexp(-eps * hprev * p.invM + thW, b);
+            }
+        }
+    }
+
     int64_t c[DPT];
     double dmax = 0.0, amax = 0.0;
     uint32_t gflags = 0;
@@ -472,30 +555,44 @@ __global__ __launch_bounds__(NT) void k4_backmap_carry(KParams p)
         const uint64_t i = i0 + t;
         c[t] = 0;
         if (i < p.ncoef) {
-            const double xv = x_value<KIND>(p, q, (uint32_t)i, thW);
-            const double r = rint(xv);
-            const double ax = fabs(xv);
-            dmax = fmax(dmax, fabs(xv - r));
+            const double r = rint(xv[t]);
+            const double ax = fabs(xv[t]);
+            dmax = fmax(dmax, fabs(xv[t] - r));
             amax = fmax(amax, ax);
             if (ax < 4503599627370496.0) c[t] = (int64_t)r;  // |x| < 2^52
             if (DIAG) {
                 p.dbg_c[i] = c[t];
-                if (p.dbg_x) p.dbg_x[i] = xv;
+                if (p.dbg_x) p.dbg_x[i] = xv[t];
             }
             if (KIND != K_FULL && i == 0 && (c[t] & ((1ll << b) - 1)) != 0) gflags |= TM_GUARD_C0;
         }
     }
+    // guard: reduce over the workgroup, then one atomic per field and only
+    // when it raises the stored maximum (non-negative doubles order like
+    // their bit patterns)
     dmax = wave_max(dmax);
     amax = wave_max(amax);
-    if ((tid & 63) == 0) {
-        atomicMax(reinterpret_cast<unsigned long long*>(&p.guard->max_dist),
-                  (unsigned long long)__double_as_longlong(dmax));
-        atomicMax(reinterpret_cast<unsigned long long*>(&p.guard->max_abs),
-                  (unsigned long long)__double_as_longlong(amax));
-        uint32_t f = (dmax >= 0.25 ? TM_GUARD_DIST : 0u) | (amax >= 1125899906842624.0 ? TM_GUARD_ABS : 0u);
+    if (gflags) atomicOr(&sGF, gflags);
+    if (lane == 0) {
+        sGD[wv] = dmax;
+        sGA[wv] = amax;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w2 = 1; w2 < NW; w2++) {
+            dmax = fmax(dmax, sGD[w2]);
+            amax = fmax(amax, sGA[w2]);
+        }
+        uint64_t* gd = reinterpret_cast<uint64_t*>(&p.guard->max_dist);
+        uint64_t* ga = reinterpret_cast<uint64_t*>(&p.guard->max_abs);
+        const uint64_t bd = (uint64_t)__double_as_longlong(dmax);
+        const uint64_t ba = (uint64_t)__double_as_longlong(amax);
+        if (bd > ld_rlx(gd)) atomicMax(reinterpret_cast<unsigned long long*>(gd), (unsigned long long)bd);
+        if (ba > ld_rlx(ga)) atomicMax(reinterpret_cast<unsigned long long*>(ga), (unsigned long long)ba);
+        const uint32_t f = sGF | (dmax >= 0.25 ? TM_GUARD_DIST : 0u) |
+                           (amax >= 1125899906842624.0 ? TM_GUARD_ABS : 0u);
         if (f) atomicOr(&p.guard->flags, f);
     }
-    if (gflags) atomicOr(&p.guard->flags, gflags);
     if (DIAG) return;
 
     if (KIND == K_HI) {
@@ -511,9 +608,9 @@ __global__ __launch_bounds__(NT) void k4_backmap_carry(KParams p)
     unsigned __int128 l = 0;
 #pragma unroll
     for (int t = 0; t < DPT; t++) {
-        int64_t s = c[t] + carry;
-        l |= (unsigned __int128)(uint64_t)(s & mask) << (t * b);
-        carry = s >> b;
+        int64_t sv = c[t] + carry;
+        l |= (unsigned __int128)(uint64_t)(sv & mask) << (t * b);
+        carry = sv >> b;
     }
     const int B = DPT * b;
     CarryF f;
@@ -526,78 +623,101 @@ __global__ __launch_bounds__(NT) void k4_backmap_carry(KParams p)
         f.T = t > (unsigned __int128)INT64_MAX ? INT64_MAX : (int64_t)(uint64_t)t;
     }
 
-    // inclusive scan of carry functions over the workgroup (Hillis-Steele)
-    sA[tid] = f.A;
-    sT[tid] = f.T;
-    __syncthreads();
-    for (int d = 1; d < NT; d <<= 1) {
-        CarryF mine = {sA[tid], sT[tid]};
-        CarryF prev = {0, 0};
-        if (tid >= d) prev = CarryF{sA[tid - d], sT[tid - d]};
-        __syncthreads();
-        if (tid >= d) {
-            CarryF r = compose(prev, mine);
-            sA[tid] = r.A;
-            sT[tid] = r.T;
-        }
-        __syncthreads();
+    // inclusive scan of carry functions: within each wave by shuffles, then
+    // across the NW waves through LDS
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t pa = __shfl_up(f.A, d), pt = __shfl_up(f.T, d);
+        if (lane >= d) f = compose(CarryF{pa, pt}, f);
     }
+    if (lane == 63) {
+        sWA[wv] = f.A;
+        sWT[wv] = f.T;
+    }
+    __syncthreads();
+    CarryF pre = {0, INT64_MAX};
+    bool have_pre = false;
+    for (int w2 = 0; w2 < wv; w2++) {
+        const CarryF t = {sWA[w2], sWT[w2]};
+        pre = have_pre ? compose(pre, t) : t;
+        have_pre = true;
+    }
+    if (have_pre) f = compose(pre, f);
+    // exclusive prefix of this thread
+    const int64_t ea = __shfl_up(f.A, 1), et = __shfl_up(f.T, 1);
+    CarryF excl = lane > 0 ? CarryF{ea, et} : pre;
+    const bool have_excl = lane > 0 || have_pre;
 
-    // decoupled look-back over workgroups: status[4g..4g+3] = flag, A, T, C
-    if (tid == 0) {
-        const CarryF agg = {sA[NT - 1], sT[NT - 1]};
+    // decoupled look-back, one wavefront.  status[2g] = state | A (aggregate)
+    // or state | C (inclusive carry-out), status[2g+1] = state | T.  Values
+    // are carries (|c| < 2^53) and thresholds clamped to +-2^61, which act
+    // as +-infinity for such carries.
+    if (wv == 0) {
+        CarryF agg = {sWA[0], sWT[0]};
+        for (int w2 = 1; w2 < NW; w2++) agg = compose(agg, CarryF{sWA[w2], sWT[w2]});
         uint64_t* st = p.status;
-        st_rlx(&st[4 * g + 1], (uint64_t)agg.A);
-        st_rlx(&st[4 * g + 2], (uint64_t)agg.T);
-        st_rel(&st[4 * g + 0], 1);
         int64_t cin = 0;
         if (g > 0) {
-            bool have = false;
-            CarryF acc = {0, 0};
-            int64_t j = (int64_t)g - 1;
-            while (true) {
-                uint64_t fl;
-                uint32_t spins = 0;
-                while ((fl = ld_acq(&st[4 * j])) == 0) {
-                    if (++spins > SPIN_LIMIT) break;
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                if (fl == 0) {
-                    atomicOr(&p.guard->flags, TM_GUARD_SPIN);
-                    cin = 0;
-                    break;
-                }
-                if (fl == 2) {
-                    int64_t C = (int64_t)ld_rlx(&st[4 * j + 3]);
-                    cin = have ? apply(acc, C) : C;
-                    break;
-                }
-                CarryF fj = {(int64_t)ld_rlx(&st[4 * j + 1]), (int64_t)ld_rlx(&st[4 * j + 2])};
-                acc = have ? compose(fj, acc) : fj;
-                have = true;
-                if (j == 0) {  // the number starts with carry 0
-                    cin = apply(acc, 0);
-                    break;
-                }
-                j--;
+            if (lane == 0) {
+                st_rlx(&st[2 * g + 1], pack62(1, agg.T));
+                st_rlx(&st[2 * g + 0], pack62(1, agg.A));
             }
+            CarryF acc = {0, INT64_MAX};
+            bool have_acc = false;
+            int64_t e = (int64_t)g - 1;
+            bool timed_out = false;
+            while (true) {
+                const int64_t idx = e - 63 + lane;
+                bool incl = true;
+                CarryF fv = {0, INT64_MAX};  // before the number: carry 0
+                if (idx >= 0) {
+                    const uint64_t wa = poll_word(&st[2 * idx], timed_out);
+                    if ((wa >> 62) == 2) {
+                        fv.A = unpack62(wa);
+                    } else if ((wa >> 62) == 1) {
+                        const uint64_t wt = poll_word(&st[2 * idx + 1], timed_out);
+                        fv.A = unpack62(wa);
+                        fv.T = unpack62(wt);
+                        fv.T = fv.T <= V62_MIN ? INT64_MIN : fv.T >= V62_MAX ? INT64_MAX : fv.T;
+                        incl = false;
+                    }
+                }
+                const bool any_incl = __ballot(incl) != 0;
+                // ordered reduction: lane 0 ends with f_(idx 63) o ... o f_(idx 0)
+                CarryF r = fv;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int64_t oa = __shfl_down(r.A, d), ot = __shfl_down(r.T, d);
+                    if ((lane & (2 * d - 1)) == 0) r = compose(r, CarryF{oa, ot});
+                }
+                r.A = __shfl(r.A, 0);
+                r.T = __shfl(r.T, 0);
+                const CarryF tot = have_acc ? compose(r, acc) : r;
+                if (any_incl) {
+                    cin = apply(tot, 0);
+                    break;
+                }
+                acc = tot;
+                have_acc = true;
+                e -= 64;
+            }
+            if (__ballot(timed_out) != 0 && lane == 0) atomicOr(&p.guard->flags, TM_GUARD_SPIN);
         }
-        const int64_t cout = apply(agg, cin);
-        st_rlx(&st[4 * g + 3], (uint64_t)cout);
-        st_rel(&st[4 * g + 0], 2);
-        s_cin = cin;
+        if (lane == 0) {
+            st_rlx(&st[2 * g + 0], pack62(2, apply(agg, cin)));
+            s_cin = cin;
+        }
     }
     __syncthreads();
 
     // final digits with the true carry-in
-    int64_t cin = s_cin;
-    if (tid > 0) cin = apply(CarryF{sA[tid - 1], sT[tid - 1]}, cin);
-    carry = cin;
+    const int64_t cwg = s_cin;
+    carry = have_excl ? apply(excl, cwg) : cwg;
 #pragma unroll
     for (int t = 0; t < DPT; t++) {
-        int64_t s = c[t] + carry;
-        sd[tid * DPT + t] = (uint16_t)(s & mask);
-        carry = s >> b;
+        int64_t sv = c[t] + carry;
+        sd[tid * DPT + t] = (uint16_t)(sv & mask);
+        carry = sv >> b;
     }
     __syncthreads();
 
@@ -608,7 +728,7 @@ __global__ __launch_bounds__(NT) void k4_backmap_carry(KParams p)
     const int64_t hi_o = ob1 < (int64_t)p.out_bits ? ob1 : (int64_t)p.out_bits;
     if (hi_o <= lo_o) return;
     const int64_t l0 = lo_o >> 6, l1 = (hi_o - 1) >> 6;
-    for (int64_t li = l0 + tid; li <= l1; li += NT) {
+    for (int64_t li = l0 + tid; li <= l1; li += NT4) {
         const int64_t sl = li * 64 + (int64_t)p.off;  // S bit of output bit 64 li
         const int64_t a = sl > sb0 ? sl : sb0;
         const int64_t z = sl + 64 < sb1 ? sl + 64 : sb1;

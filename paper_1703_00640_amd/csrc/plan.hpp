@@ -15,11 +15,11 @@
 
 namespace tmul {
 
-constexpr int B_TRUNC = 11;          // digit size of the truncated products
+constexpr int B_TRUNC = 11;          // digit size of the truncated products (8..15)
 constexpr int B_FULL = 16;           // digit size of the full product
 constexpr uint64_t TRUNC_MIN_BITS = 1025;  // below: full product + extraction
 constexpr uint32_t L2_MAX = 1024, L1_MAX = 4096;
-constexpr int DPW_HOST = 7 * 256;    // digits per K4 workgroup
+constexpr int DPW_HOST = 7 * 1024;   // digits per K4 workgroup
 
 struct Plan {
     int req_kind = 0;   // requested tm_kind
@@ -36,7 +36,7 @@ struct Plan {
     uint64_t off = 0, out_bits = 0, out_limbs = 0;
     uint64_t ncoef = 0, ncover = 0;
     uint32_t nstatus = 0;
-    size_t o_za = 0, o_zb = 0, o_status = 0, o_ticket = 0, o_guard = 0, ws_bytes = 0;
+    size_t o_za = 0, o_zb = 0, o_status = 0, o_ticket = 0, o_guard = 0, o_theta = 0, ws_bytes = 0;
 };
 
 inline int lg_ceil(uint64_t x)
@@ -98,7 +98,7 @@ inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P)
     P.L = (n + 63) / 64;
     const int bt = b_trunc ? b_trunc : B_TRUNC;
     const int bf = b_full ? b_full : B_FULL;
-    if (bt < 8 || bt > 16 || bf < 8 || bf > 16) return false;
+    if (bt < 8 || bt > 15 || bf < 8 || bf > 16) return false;
     P.via_full = kind != TM_FULL && n < TRUNC_MIN_BITS;
     P.kind = P.via_full ? TM_FULL : kind;
 
@@ -133,6 +133,7 @@ inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P)
         if (P.lam < 2) P.lam = 2;
         if (P.lam > 9) return false;
         P.jmax = (80 + b - 1) / b;
+        if (P.lam + (int)P.jmax > 32) return false;  // wrap terms must fit the K4 halo
         if (P.N < (uint64_t)(2 * P.lam + P.jmax + 2)) return false;
         P.off = kind == TM_LO ? (uint64_t)b : (P.N + 3) * (uint64_t)b - n;
         P.out_bits = n;
@@ -152,6 +153,7 @@ inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P)
     P.o_status = o; o = align256(o + (size_t)P.nstatus * 32);
     P.o_ticket = o; o = align256(o + 8);
     P.o_guard = o; o = align256(o + sizeof(tm_guard));
+    P.o_theta = o; o = align256(o + 2 * sizeof(double));
     P.ws_bytes = o;
     return true;
 }

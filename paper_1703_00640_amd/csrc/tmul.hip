@@ -16,6 +16,8 @@
 
 using namespace tmul;
 
+static_assert(DPW == DPW_HOST, "K4 digits per workgroup must match the planner");
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -92,8 +94,14 @@ template <int KIND>
 bool launch_k1(uint32_t L1, const KParams& p, hipStream_t s)
 {
     switch (L1) {
-#define X(V) \
-    case V: hipLaunchKernelGGL((k1_split_map_col<V, w_for(V), KIND>), dim3(p.L2 / w_for(V), 2), dim3(NT), 0, s, p); return true;
+#define X(V)                                                                                  \
+    case V:                                                                                   \
+        if constexpr (k1_fits(V, w_for(V), KIND)) {                                           \
+            hipLaunchKernelGGL((k1_split_map_col<V, w_for(V), KIND>), dim3(p.L2 / w_for(V), 2), \
+                               dim3(NT), 0, s, p);                                            \
+            return true;                                                                      \
+        }                                                                                     \
+        return false;
         TM_L1_LIST(X)
 #undef X
     }
@@ -130,9 +138,9 @@ template <bool DIAG>
 void launch_k4(int kind, const KParams& p, hipStream_t s)
 {
     dim3 g(p.nstatus);
-    if (kind == TM_FULL) hipLaunchKernelGGL((k4_backmap_carry<K_FULL, DIAG>), g, dim3(NT), 0, s, p);
-    else if (kind == TM_LO) hipLaunchKernelGGL((k4_backmap_carry<K_LO, DIAG>), g, dim3(NT), 0, s, p);
-    else hipLaunchKernelGGL((k4_backmap_carry<K_HI, DIAG>), g, dim3(NT), 0, s, p);
+    if (kind == TM_FULL) hipLaunchKernelGGL((k4_backmap_carry<K_FULL, DIAG>), g, dim3(NT4), 0, s, p);
+    else if (kind == TM_LO) hipLaunchKernelGGL((k4_backmap_carry<K_LO, DIAG>), g, dim3(NT4), 0, s, p);
+    else hipLaunchKernelGGL((k4_backmap_carry<K_HI, DIAG>), g, dim3(NT4), 0, s, p);
 }
 
 bool launch_k1_any(int kind, const KParams& p, hipStream_t s)
@@ -193,6 +201,7 @@ void fill_params(const Plan& P, const uint64_t* u, const uint64_t* v, uint64_t* 
     p.status = reinterpret_cast<uint64_t*>(base + P.o_status);
     p.ticket = reinterpret_cast<uint32_t*>(base + P.o_ticket);
     p.guard = guard ? guard : reinterpret_cast<tm_guard*>(base + P.o_guard);
+    p.theta = reinterpret_cast<double*>(base + P.o_theta);
     p.tw = tw;
 }
 

@@ -183,19 +183,21 @@ def test_config_n2_24_parity():
     say("  guard lo %.4g hi %.4g full %.4g" % (glo.max_dist, ghi.max_dist, gfu.max_dist))
 
 
-def test_b16_truncated_trips_guard_and_checked_recovers(monkeypatch):
-    """Negative control: the configs' literal b = 16 for the truncated
-    product exceeds the FP64 budget (3b + lg N > 53); the guard must trip,
-    and the checked entry point must fall back and return the right value."""
+def test_large_b_truncated_trips_guard_and_checked_recovers(monkeypatch):
+    """Negative control for the configs' literal b = 16 on the truncated
+    product: any b with 3b + lg N well above 53 fails in FP64.  Forced here
+    to b = 15 (the largest truncated digit size the kernels store); the guard
+    must trip, and the checked entry point must fall back (b = 13) and
+    return the right value."""
     tm = _tm()
     n = 1 << 16
     u, v = inputs.operand_pair(n, 3)
-    monkeypatch.setenv("TM_FORCE_B", "16")
+    monkeypatch.setenv("TM_FORCE_B", "15")
     lo, g = run_kind("lo", u, v, n)
-    say("  b=16 low product guard:", g.as_dict())
-    assert g.b == 16 and g.flags != 0
+    say("  b=15 low product guard:", g.as_dict())
+    assert g.b == 15 and g.flags != 0
     out, g2 = tm.mul_checked("lo", to_dev(u), to_dev(v), n)
-    assert g2.flags == 0 and g2.b == 14
+    assert g2.flags == 0 and g2.b == 13
     assert np.array_equal(to_host(out), oracle.mul_lo(u, v, n))
 
 
