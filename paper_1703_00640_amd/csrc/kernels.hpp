@@ -170,27 +170,118 @@ __device__ __forceinline__ void clear_state(const KParams& p, uint32_t gid, uint
 
 // ------------------------------------------------------------------- K1
 
-// K1 tile area in double2 units: the tile, or the staged digits of the
-// truncated products (int16, row stride 2W + LMAX - 1), whichever is larger.
-constexpr int k1_nd(int W) { return 2 * W + LMAX - 1; }
-constexpr int k1_area(int L1, int W, int KIND)
+// Digits of one K1 tile row.  A row holds complex points m0 .. m0+W-1, i.e.
+// reals 2 m0 .. 2 m0 + 2W - 1; the truncated products' stencil also reads
+// the LMAX - 1 digits below.  The row's limbs are fetched once (independent
+// loads) and every digit is cut from registers.
+constexpr int k1_lo(int KIND) { return KIND == K_FULL ? 0 : LMAX - 1; }
+constexpr int k1_nd(int W, int KIND) { return 2 * W + k1_lo(KIND); }
+constexpr int k1_nlw(int ND) { return ((ND + 1) * 16 + 63) / 64 + 1; }
+
+template <int NLW>
+__device__ __forceinline__ uint64_t pick_limb(const uint64_t (&lim)[NLW], int i)
 {
-    return KIND == K_FULL || L1 * W * 16 >= L1 * k1_nd(W) * 2 ? L1 * W : (L1 * k1_nd(W) * 2 + 15) / 16;
+    uint64_t r = 0;
+#pragma unroll
+    for (int k = 0; k < NLW; k++) r = (k == i) ? lim[k] : r;
+    return r;
 }
-constexpr bool k1_fits(int L1, int W, int KIND) { return k1_area(L1, W, KIND) * 16 <= 65536; }
+
+// d[t] = balanced digit at index kf + t: cyclic mod N for the truncated
+// products (their digits are all of the plain kind below N); for the full
+// product the top digit keeps its carry and indices >= digits are zero.
+template <int ND, int KIND>
+__device__ __forceinline__ void row_digits(const KParams& p, const uint64_t* x, int64_t kf,
+                                           int32_t (&d)[ND])
+{
+    constexpr int NLW = k1_nlw(ND);
+    const int b = p.b;
+    const int64_t top = KIND == K_FULL ? (int64_t)p.digits - 1 : (int64_t)p.N;
+    const bool fast = kf >= 0 && (KIND == K_FULL ? kf + ND <= top : true);
+    if (KIND == K_FULL && kf > top) {
+#pragma unroll
+        for (int t = 0; t < ND; t++) d[t] = 0;
+        return;
+    }
+    if (fast) {
+        const int64_t p0 = (kf - 1) * b - p.shift;  // bit of the first 2b-bit field
+        const int64_t l0 = p0 >= 0 ? p0 >> 6 : -((63 - p0) >> 6);
+        uint64_t lim[NLW];
+#pragma unroll
+        for (int i = 0; i < NLW; i++) {
+            const int64_t li = l0 + i;
+            uint64_t v = (li >= 0 && li < (int64_t)p.L) ? x[li] : 0;
+            if (li == (int64_t)p.L - 1 && (p.n & 63)) v &= (1ull << (p.n & 63)) - 1;
+            lim[i] = v;
+        }
+        const int64_t mask = (1ll << b) - 1, h = 1ll << (b - 1);
+#pragma unroll
+        for (int t = 0; t < ND; t++) {
+            const int rel = (int)((kf + t - 1) * b - p.shift - l0 * 64);
+            const int li = rel >> 6, sh = rel & 63;
+            const uint64_t lo = pick_limb(lim, li), hi = pick_limb(lim, li + 1);
+            const uint64_t w = sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
+            const int64_t dprev = (int64_t)(w & mask), dd = (int64_t)((w >> b) & mask);
+            d[t] = (int32_t)(dd - (dd >= h ? (1ll << b) : 0) + (dprev >= h ? 1 : 0));
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < ND; t++) {
+            int64_t k = kf + t;
+            if (KIND == K_FULL) {
+                d[t] = k <= top ? (int32_t)bal_digit(p, x, k, p.digits, true) : 0;
+            } else {
+                if (k < 0) k += p.N;
+                d[t] = (int32_t)bal_digit(p, x, k, p.digits, false);
+            }
+        }
+    }
+}
+
+// G_(2m0+2c+e) for one row:
+//   full: the digits themselves;
+//   low:  G = alpha* U   (Prop. approximating alpha*), cyclic indices;
+//   high: G = gamma* F'  with F'_k = F_k + 2^(-kb) F_N  (F mod C by eq.
+//         reduction-modC with rho ~ 2^b, Prop. approximating gamma-dagger).
+template <int W, int KIND>
+__device__ __forceinline__ void row_values(const KParams& p, const uint64_t* x, uint32_t m0,
+                                           double FN, double2 (&g)[W])
+{
+    constexpr int ND = k1_nd(W, KIND), LO = k1_lo(KIND);
+    int32_t d[ND];
+    row_digits<ND, KIND>(p, x, 2 * (int64_t)m0 - LO, d);
+    if constexpr (KIND == K_FULL) {
+#pragma unroll
+        for (int c = 0; c < W; c++) g[c] = make_double2((double)d[2 * c], (double)d[2 * c + 1]);
+    } else {
+        const uint32_t N = p.N;
+#pragma unroll
+        for (int c = 0; c < W; c++) {
+            double s[2] = {0.0, 0.0};
+#pragma unroll
+            for (int e = 0; e < 2; e++) {
+                const uint32_t j = 2 * m0 + 2 * c + e;
+#pragma unroll
+                for (int r = 0; r < LMAX; r++) {
+                    if (r < p.lam) {
+                        const uint32_t k = j >= (uint32_t)r ? j - r : j + N - r;
+                        double f = (double)d[2 * c + e - r + LO];
+                        if (KIND == K_HI && k < p.jmax) f += ldexp(FN, -(int)k * p.b);
+                        s[e] = fma(coef_fwd(KIND, k, r, p.invN, p.cf[r]), f, s[e]);
+                    }
+                }
+            }
+            g[c] = make_double2(s[0], s[1]);
+        }
+    }
+}
 
 template <int L1, int W, int KIND>
 __global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
 {
     static_assert(L1 * W <= TILE, "tile too large");
-    static_assert(k1_fits(L1, W, KIND), "K1 LDS area too large");
-    // ND digits per tile row: the row's 2W reals need digits
-    // [2 m0 - lam + 1, 2 m0 + 2W) (mod N); they are extracted once into the
-    // tile area (int16: truncated digits have at most 15 bits) before the
-    // map is evaluated.
-    constexpr int ND = k1_nd(W);
     constexpr int PER = (L1 * W + NT - 1) / NT;
-    __shared__ double2 tile[k1_area(L1, W, KIND)];
+    __shared__ double2 tile[L1 * W];
     __shared__ double s_FN;
     const int op = blockIdx.y;
     const uint64_t* x = op ? p.v : p.u;
@@ -200,77 +291,31 @@ __global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
     const int tid = threadIdx.x;
 
     if (op == 0) clear_state(p, blockIdx.x * NT + tid, gridDim.x * NT);
-
-    if constexpr (KIND == K_FULL) {
-        for (int e = tid; e < L1 * W; e += NT) {
-            const int c = e % W, j1 = e / W;
-            const uint32_t j = 2 * ((uint32_t)j1 * L2 + c0 + c);
-            const double g0 = j < p.digits ? (double)bal_digit(p, x, j, p.digits, true) : 0.0;
-            const double g1 = j + 1 < p.digits ? (double)bal_digit(p, x, j + 1, p.digits, true) : 0.0;
-            tile[e] = make_double2(g0, g1);
-        }
-        __syncthreads();
-    } else {
-        const uint32_t N = p.N;
-        const int lam = p.lam;
-        int16_t* dg = reinterpret_cast<int16_t*>(tile);
-        if (KIND == K_HI && tid == 0) {
-            s_FN = (double)bal_digit(p, x, N, p.digits, true);
-            if (blockIdx.x == 0) p.theta[op] = hi_theta(p, x);
-        }
-        // phase A: digits, row-major [j1][t], t = 0 .. 2W + lam - 2
-        const int nd = 2 * W + lam - 1;
-        for (int e = tid; e < L1 * ND; e += NT) {
-            const int j1 = e / ND, t = e % ND;
-            if (t >= nd) continue;
-            const int64_t k0 = 2 * ((int64_t)j1 * L2 + c0) - lam + 1 + t;  // > -N, < N
-            const uint32_t k = (uint32_t)(k0 < 0 ? k0 + (int64_t)N : k0);
-            dg[j1 * ND + t] = (int16_t)bal_digit(p, x, k, p.digits, KIND == K_HI);
-        }
-        __syncthreads();
-        const double FN = KIND == K_HI ? s_FN : 0.0;
-        // phase B: G_j = sum_{r<lam} coef_{(j-r) mod N, r} F'_((j-r) mod N)
-        double2 gv[PER];
-#pragma unroll
-        for (int q = 0; q < PER; q++) {
-            const int e = tid + q * NT;
-            if (L1 * W % NT == 0 || e < L1 * W) {
-                const int c = e % W, j1 = e / W;
-                const uint32_t j = 2 * ((uint32_t)j1 * L2 + c0 + c);
-                const int16_t* row = dg + j1 * ND + 2 * c;  // row[t] = F at j + 1 - lam + t
-                double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-                for (int r = 0; r < LMAX; r++) {
-                    if (r < lam) {
-                        const uint32_t k0 = j >= (uint32_t)r ? j - r : j + N - r;
-                        const uint32_t k1 = j + 1 >= (uint32_t)r ? j + 1 - r : j + 1 + N - r;
-                        double f0 = (double)row[lam - 1 - r], f1 = (double)row[lam - r];
-                        if (KIND == K_HI) {
-                            if (k0 < p.jmax) f0 += ldexp(FN, -(int)k0 * p.b);
-                            if (k1 < p.jmax) f1 += ldexp(FN, -(int)k1 * p.b);
-                        }
-                        s0 = fma(coef_fwd(KIND, k0, r, p.invN, p.cf[r]), f0, s0);
-                        s1 = fma(coef_fwd(KIND, k1, r, p.invN, p.cf[r]), f1, s1);
-                    }
-                }
-                gv[q] = make_double2(s0, s1);
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PER; q++) {
-            const int e = tid + q * NT;
-            if (L1 * W % NT == 0 || e < L1 * W) tile[e] = gv[q];
-        }
-        __syncthreads();
+    if (KIND == K_HI && tid == 0) {
+        s_FN = (double)bal_digit(p, x, p.N, p.digits, true);
+        if (blockIdx.x == 0) p.theta[op] = hi_theta(p, x);
     }
+    __syncthreads();
+    const double FN = KIND == K_HI ? s_FN : 0.0;
+    // one row (W complex points) per thread
+    for (int j1 = tid; j1 < L1; j1 += NT) {
+        double2 g[W];
+        row_values<W, KIND>(p, x, (uint32_t)j1 * L2 + c0, FN, g);
+#pragma unroll
+        for (int c = 0; c < W; c++) tile[j1 * W + c] = g[c];
+    }
+    __syncthreads();
     tile_fft<L1, W, NT, false, true>(tile, p.tw, p.M / L1);
-    for (int e = tid; e < L1 * W; e += NT) {
-        const int c = e % W, k1 = e / W;
-        const uint32_t col = c0 + c;
-        double2 val = tile[e];
-        if (k1 != 0 && col != 0) val = cmul(val, tw_get<false>(p.tw, col * (uint32_t)k1));
-        dst[(size_t)k1 * L2 + col] = val;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int e = tid + q * NT;
+        if (L1 * W % NT == 0 || e < L1 * W) {
+            const int c = e % W, k1 = e / W;
+            const uint32_t col = c0 + c;
+            double2 val = tile[e];
+            if (k1 != 0 && col != 0) val = cmul(val, tw_get<false>(p.tw, col * (uint32_t)k1));
+            dst[(size_t)k1 * L2 + col] = val;
+        }
     }
 }
 
@@ -305,11 +350,24 @@ __global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
     const uint32_t L1 = p.L1;
     const uint32_t k1 = blockIdx.x;
     const uint32_t k1m = (L1 - k1) % L1;
-    for (int e = threadIdx.x; e < 4 * L2; e += NT) {
-        const int r = e / L2, j2 = e % L2;
-        const uint32_t row = r < 2 ? k1 : k1m;
-        const double2* src = (r & 1) ? p.zb : p.za;
-        rows[e] = src[(size_t)row * L2 + j2];
+    {
+        constexpr int PL = (4 * L2 + NT - 1) / NT;
+        double2 v[PL];
+#pragma unroll
+        for (int q = 0; q < PL; q++) {
+            const int e = threadIdx.x + q * NT;
+            if (4 * L2 % NT == 0 || e < 4 * L2) {
+                const int r = e / L2, j2 = e % L2;
+                const uint32_t row = r < 2 ? k1 : k1m;
+                const double2* src = (r & 1) ? p.zb : p.za;
+                v[q] = src[(size_t)row * L2 + j2];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PL; q++) {
+            const int e = threadIdx.x + q * NT;
+            if (4 * L2 % NT == 0 || e < 4 * L2) rows[e] = v[q];
+        }
     }
     __syncthreads();
     tile_fft<L2, 4, NT, false, false, L2>(rows, p.tw, p.M / L2);
@@ -360,15 +418,26 @@ __global__ __launch_bounds__(NT) void k3_col_inverse(KParams p)
     __shared__ double2 tile[L1 * W];
     const uint32_t L2 = p.L2;
     const uint32_t c0 = blockIdx.x * W;
-    for (int e = threadIdx.x; e < L1 * W; e += NT) {
-        const int c = e % W, k1 = e / W;
-        tile[e] = p.za[(size_t)k1 * L2 + c0 + c];
+    constexpr int PER = (L1 * W + NT - 1) / NT;
+    {
+        double2 v[PER];
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int e = threadIdx.x + q * NT;
+            if (L1 * W % NT == 0 || e < L1 * W) v[q] = p.za[(size_t)(e / W) * L2 + c0 + e % W];
+        }
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int e = threadIdx.x + q * NT;
+            if (L1 * W % NT == 0 || e < L1 * W) tile[e] = v[q];
+        }
     }
     __syncthreads();
     tile_fft<L1, W, NT, true, true>(tile, p.tw, p.M / L1);
-    for (int e = threadIdx.x; e < L1 * W; e += NT) {
-        const int c = e % W, j1 = e / W;
-        p.za[(size_t)j1 * L2 + c0 + c] = tile[e];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int e = threadIdx.x + q * NT;
+        if (L1 * W % NT == 0 || e < L1 * W) p.za[(size_t)(e / W) * L2 + c0 + e % W] = tile[e];
     }
 }
 

@@ -94,14 +94,8 @@ template <int KIND>
 bool launch_k1(uint32_t L1, const KParams& p, hipStream_t s)
 {
     switch (L1) {
-#define X(V)                                                                                  \
-    case V:                                                                                   \
-        if constexpr (k1_fits(V, w_for(V), KIND)) {                                           \
-            hipLaunchKernelGGL((k1_split_map_col<V, w_for(V), KIND>), dim3(p.L2 / w_for(V), 2), \
-                               dim3(NT), 0, s, p);                                            \
-            return true;                                                                      \
-        }                                                                                     \
-        return false;
+#define X(V) \
+    case V: hipLaunchKernelGGL((k1_split_map_col<V, w_for(V), KIND>), dim3(p.L2 / w_for(V), 2), dim3(NT), 0, s, p); return true;
         TM_L1_LIST(X)
 #undef X
     }
