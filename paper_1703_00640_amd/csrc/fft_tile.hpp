@@ -4,9 +4,8 @@
 // FFTs, pointwise product, inverse FFT).  A tile holds NB independent
 // sequences of length P; a Stockham autosort schedule of radix-3/4/8/2
 // stages transforms all of them in place, one LDS round trip per stage.
-// Twiddles come from a two-level table of exp(-2 pi i e / M) (M = whole
-// transform length), so every twiddle is the product of two correctly
-// rounded table entries.
+// Stage twiddles come from an LDS copy of exp(-2 pi i e / P), e < P, so no
+// stage waits on global memory.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -35,13 +34,39 @@ __device__ __forceinline__ double2 mul_mi(double2 a)
     return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
 }
 
-// exp(-2 pi i e / M), or its conjugate for the inverse direction
+// exp(-2 pi i e / M), or its conjugate for the inverse direction, from the
+// two-level global table (used outside the LDS tiles)
 template <bool INV>
 __device__ __forceinline__ double2 tw_get(const Tw& t, uint32_t e)
 {
     double2 w = cmul(t.lo[e & t.mask], t.hi[e >> t.shift]);
     return INV ? cconj(w) : w;
 }
+
+// Twiddles base * step^q, q < Q, for a thread whose elements form an
+// arithmetic progression of exponents.  base and step are fetched from the
+// global table at kernel start (their latency hides behind the tile work);
+// powers use at most four products each.
+template <int Q>
+struct TwSeq {
+    double2 pw[4];
+    double2 base;
+    __device__ __forceinline__ void init(double2 b, double2 step)
+    {
+        base = b;
+        pw[0] = step;
+#pragma unroll
+        for (int i = 1; i < 4; i++) pw[i] = cmul(pw[i - 1], pw[i - 1]);
+    }
+    __device__ __forceinline__ double2 at(int q) const
+    {
+        double2 w = base;
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+            if ((1 << i) < Q && ((q >> i) & 1)) w = cmul(w, pw[i]);
+        return w;
+    }
+};
 
 // ------------------------------------------------------------- codelets
 
@@ -116,18 +141,37 @@ constexpr int pick_radix(int rem)
     return rem % 3 == 0 ? 3 : rem == 16 ? 4 : rem % 8 == 0 ? 8 : rem % 4 == 0 ? 4 : 2;
 }
 
+// LDS tiles are padded by one element after every 16, which spreads the
+// power-of-two strides of the Stockham stages over the LDS banks.
+__device__ __forceinline__ int pidx(int e) { return e + (e >> 4); }
+constexpr int padded(int n) { return n + (n >> 4) + 1; }
+
 // Element (j, c) of the tile: sequence c, position j.
-//   COLS: sequences interleaved (address j*NB + c)  - column tiles
-//   rows: sequences contiguous  (address c*RS + j)   - row tiles
+//   COLS: sequences interleaved (index j*NB + c)  - column tiles
+//   rows: sequences contiguous  (index c*RS + j)   - row tiles
 template <bool COLS, int NB, int RS>
 __device__ __forceinline__ int tile_addr(int j, int c)
 {
-    return COLS ? j * NB + c : c * RS + j;
+    return pidx(COLS ? j * NB + c : c * RS + j);
+}
+
+// LDS twiddle table length for a sub-transform of length P, and lookup of
+// exp(-2 pi i e / P), e < P.
+constexpr int twl_size(int P) { return P % 2 == 0 ? P / 2 : P; }
+template <int P>
+__device__ __forceinline__ double2 tw_half(const double2* twl, int e)
+{
+    if constexpr (P % 2 == 0) {
+        const double2 w = twl[e < P / 2 ? e : e - P / 2];
+        return e < P / 2 ? w : make_double2(-w.x, -w.y);
+    } else {
+        return twl[e];
+    }
 }
 
 // One Stockham stage of radix R after NS points have been combined.
 template <int P, int R, int NS, int NB, int NT, bool INV, bool COLS, int RS>
-__device__ __forceinline__ void fft_stage(double2* buf, const Tw& tw, uint32_t tscale)
+__device__ __forceinline__ void fft_stage(double2* buf, const double2* twl)
 {
     constexpr int BF = P / R;
     constexpr int TOT = BF * NB;
@@ -156,8 +200,8 @@ __device__ __forceinline__ void fft_stage(double2* buf, const Tw& tw, uint32_t t
             if (NS > 1 && k != 0) {
 #pragma unroll
                 for (int r = 1; r < R; r++) {
-                    uint32_t e = (uint32_t)(r * k) * ESTEP * tscale;
-                    v[q][r] = cmul(v[q][r], tw_get<INV>(tw, e));
+                    const double2 w = tw_half<P>(twl, (r * k) * ESTEP);
+                    v[q][r] = cmul(v[q][r], INV ? cconj(w) : w);
                 }
             }
             dftR<R, INV>(v[q]);
@@ -170,23 +214,35 @@ __device__ __forceinline__ void fft_stage(double2* buf, const Tw& tw, uint32_t t
 }
 
 template <int P, int NS, int NB, int NT, bool INV, bool COLS, int RS>
-__device__ __forceinline__ void fft_stages(double2* buf, const Tw& tw, uint32_t tscale)
+__device__ __forceinline__ void fft_stages(double2* buf, const double2* twl)
 {
     if constexpr (NS < P) {
         constexpr int R = pick_radix(P / NS);
-        fft_stage<P, R, NS, NB, NT, INV, COLS, RS>(buf, tw, tscale);
-        fft_stages<P, NS * R, NB, NT, INV, COLS, RS>(buf, tw, tscale);
+        fft_stage<P, R, NS, NB, NT, INV, COLS, RS>(buf, twl);
+        fft_stages<P, NS * R, NB, NT, INV, COLS, RS>(buf, twl);
     }
 }
 
-// In-place DFT of NB sequences of length P in LDS.  tscale = M / P converts
-// exponents of exp(-2 pi i / P) into exponents of the table's root.
-// Caller must __syncthreads() before (data written) - the routine ends with
-// a barrier.
+// In-place DFT of NB sequences of length P in LDS; twl is an LDS table of
+// exp(-2 pi i e / P), e < P.  Caller must __syncthreads() before (data and
+// table written); the routine ends with a barrier.
 template <int P, int NB, int NT, bool INV, bool COLS, int RS = P>
-__device__ __forceinline__ void tile_fft(double2* buf, const Tw& tw, uint32_t tscale)
+__device__ __forceinline__ void tile_fft(double2* buf, const double2* twl)
 {
-    fft_stages<P, 1, NB, NT, INV, COLS, RS>(buf, tw, tscale);
+    fft_stages<P, 1, NB, NT, INV, COLS, RS>(buf, twl);
+}
+
+// Copy the sub-transform table into LDS: the first half only when P is even
+// (exp(-2 pi i (e + P/2) / P) = -exp(-2 pi i e / P)).
+template <int P, int NT>
+__device__ __forceinline__ void load_twl(double2* twl, const double2* src)
+{
+    constexpr int H = twl_size(P);
+#pragma unroll
+    for (int q = 0; q < (H + NT - 1) / NT; q++) {
+        const int e = threadIdx.x + q * NT;
+        if (H % NT == 0 || e < H) twl[e] = src[e];
+    }
 }
 
 }  // namespace tmul

@@ -65,6 +65,8 @@ struct KParams {
     tm_guard* guard;
     double* theta;      // high product: theta_U, theta_V (written by K1)
     Tw tw;
+    const double2* tw1; // exp(-2 pi i e / L1), e < L1
+    const double2* tw2; // exp(-2 pi i e / L2), e < L2
     int64_t* dbg_c;     // diagnostic outputs (tm_coefficients) or null
     double* dbg_x;
 };
@@ -281,7 +283,8 @@ __global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
 {
     static_assert(L1 * W <= TILE, "tile too large");
     constexpr int PER = (L1 * W + NT - 1) / NT;
-    __shared__ double2 tile[L1 * W];
+    __shared__ double2 tile[padded(L1 * W)];
+    __shared__ double2 twl[twl_size(L1)];
     __shared__ double s_FN;
     const int op = blockIdx.y;
     const uint64_t* x = op ? p.v : p.u;
@@ -290,6 +293,14 @@ __global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
     const uint32_t c0 = blockIdx.x * W;
     const int tid = threadIdx.x;
 
+    load_twl<L1, NT>(twl, p.tw1);
+    // inter-pass twiddles exp(-2 pi i col k1 / M): this thread's elements
+    // share col = c0 + tid % W and step k1 by NT / W
+    static_assert(NT % W == 0, "W must divide NT");
+    const uint32_t colt = c0 + tid % W;
+    const uint32_t eb = (colt * (uint32_t)(tid / W)) % p.M, es = (colt * (uint32_t)(NT / W)) % p.M;
+    const double2 tb0 = p.tw.lo[eb & p.tw.mask], tb1 = p.tw.hi[eb >> p.tw.shift];
+    const double2 ts0 = p.tw.lo[es & p.tw.mask], ts1 = p.tw.hi[es >> p.tw.shift];
     if (op == 0) clear_state(p, blockIdx.x * NT + tid, gridDim.x * NT);
     if (KIND == K_HI && tid == 0) {
         s_FN = (double)bal_digit(p, x, p.N, p.digits, true);
@@ -302,19 +313,18 @@ __global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
         double2 g[W];
         row_values<W, KIND>(p, x, (uint32_t)j1 * L2 + c0, FN, g);
 #pragma unroll
-        for (int c = 0; c < W; c++) tile[j1 * W + c] = g[c];
+        for (int c = 0; c < W; c++) tile[pidx(j1 * W + c)] = g[c];
     }
     __syncthreads();
-    tile_fft<L1, W, NT, false, true>(tile, p.tw, p.M / L1);
+    tile_fft<L1, W, NT, false, true>(tile, twl);
+    TwSeq<PER> tws;
+    tws.init(cmul(tb0, tb1), cmul(ts0, ts1));
 #pragma unroll
     for (int q = 0; q < PER; q++) {
         const int e = tid + q * NT;
         if (L1 * W % NT == 0 || e < L1 * W) {
-            const int c = e % W, k1 = e / W;
-            const uint32_t col = c0 + c;
-            double2 val = tile[e];
-            if (k1 != 0 && col != 0) val = cmul(val, tw_get<false>(p.tw, col * (uint32_t)k1));
-            dst[(size_t)k1 * L2 + col] = val;
+            const int k1 = e / W;
+            dst[(size_t)k1 * L2 + colt] = cmul(tile[pidx(e)], tws.at(q));
         }
     }
 }
@@ -346,10 +356,16 @@ template <int L2>
 __global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
 {
     // rows 0,1: operands u,v at row k1; rows 2,3: at the mirror row
-    __shared__ double2 rows[4 * L2];
+    __shared__ double2 rows[padded(4 * L2)];
+    __shared__ double2 twl[twl_size(L2)];
     const uint32_t L1 = p.L1;
     const uint32_t k1 = blockIdx.x;
     const uint32_t k1m = (L1 - k1) % L1;
+    load_twl<L2, NT>(twl, p.tw2);
+    // exp(-2 pi i k / M) for bin k = rho + L1 k2 is exp(-2 pi i rho / M) times
+    // exp(-2 pi i k2 / L2): one global-table value per row
+    const double2 wr0a = p.tw.lo[k1 & p.tw.mask], wr0b = p.tw.hi[k1 >> p.tw.shift];
+    const double2 wr1a = p.tw.lo[k1m & p.tw.mask], wr1b = p.tw.hi[k1m >> p.tw.shift];
     {
         constexpr int PL = (4 * L2 + NT - 1) / NT;
         double2 v[PL];
@@ -366,13 +382,14 @@ __global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
 #pragma unroll
         for (int q = 0; q < PL; q++) {
             const int e = threadIdx.x + q * NT;
-            if (4 * L2 % NT == 0 || e < 4 * L2) rows[e] = v[q];
+            if (4 * L2 % NT == 0 || e < 4 * L2) rows[pidx(e)] = v[q];
         }
     }
     __syncthreads();
-    tile_fft<L2, 4, NT, false, false, L2>(rows, p.tw, p.M / L2);
+    tile_fft<L2, 4, NT, false, false, L2>(rows, twl);
 
     constexpr int PER = (2 * L2 + NT - 1) / NT;
+    const double2 wrow[2] = {cmul(wr0a, wr0b), cmul(wr1a, wr1b)};
     double2 qv[PER];
 #pragma unroll
     for (int t = 0; t < PER; t++) {
@@ -382,10 +399,9 @@ __global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
             const uint32_t rho = pr ? k1m : k1;
             const int mk2 = rho == 0 ? (L2 - k2) % L2 : L2 - 1 - k2;
             const int mr = 1 - pr;
-            const uint32_t k = rho + L1 * (uint32_t)k2;
-            qv[t] = pointwise_bin(rows[(2 * pr) * L2 + k2], rows[(2 * mr) * L2 + mk2],
-                                  rows[(2 * pr + 1) * L2 + k2], rows[(2 * mr + 1) * L2 + mk2],
-                                  tw_get<false>(p.tw, k));
+            qv[t] = pointwise_bin(rows[pidx((2 * pr) * L2 + k2)], rows[pidx((2 * mr) * L2 + mk2)],
+                                  rows[pidx((2 * pr + 1) * L2 + k2)], rows[pidx((2 * mr + 1) * L2 + mk2)],
+                                  cmul(wrow[pr], tw_half<L2>(twl, k2)));
         }
     }
     __syncthreads();
@@ -394,19 +410,17 @@ __global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
         const int e = threadIdx.x + t * NT;
         if (e < 2 * L2) {
             const int pr = e / L2, k2 = e % L2;
-            rows[(2 * pr) * L2 + k2] = qv[t];
+            rows[pidx((2 * pr) * L2 + k2)] = qv[t];
         }
     }
     __syncthreads();
     // inverse row DFTs of rows 0 and 2 (row stride 2*L2)
-    tile_fft<L2, 2, NT, true, false, 2 * L2>(rows, p.tw, p.M / L2);
+    tile_fft<L2, 2, NT, true, false, 2 * L2>(rows, twl);
     for (int e = threadIdx.x; e < 2 * L2; e += NT) {
         const int pr = e / L2, j2 = e % L2;
         if (pr == 1 && k1m == k1) continue;
         const uint32_t rho = pr ? k1m : k1;
-        double2 val = rows[(2 * pr) * L2 + j2];
-        if (rho != 0 && j2 != 0) val = cmul(val, tw_get<true>(p.tw, (uint32_t)j2 * rho));
-        p.za[(size_t)rho * L2 + j2] = val;
+        p.za[(size_t)rho * L2 + j2] = rows[pidx((2 * pr) * L2 + j2)];
     }
 }
 
@@ -415,29 +429,40 @@ __global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
 template <int L1, int W>
 __global__ __launch_bounds__(NT) void k3_col_inverse(KParams p)
 {
-    __shared__ double2 tile[L1 * W];
+    __shared__ double2 tile[padded(L1 * W)];
+    __shared__ double2 twl[twl_size(L1)];
     const uint32_t L2 = p.L2;
     const uint32_t c0 = blockIdx.x * W;
+    load_twl<L1, NT>(twl, p.tw1);
     constexpr int PER = (L1 * W + NT - 1) / NT;
+    static_assert(NT % W == 0, "W must divide NT");
+    const int tid = threadIdx.x;
+    const uint32_t colt = c0 + tid % W;
+    const uint32_t eb = (colt * (uint32_t)(tid / W)) % p.M, es = (colt * (uint32_t)(NT / W)) % p.M;
+    const double2 tb0 = p.tw.lo[eb & p.tw.mask], tb1 = p.tw.hi[eb >> p.tw.shift];
+    const double2 ts0 = p.tw.lo[es & p.tw.mask], ts1 = p.tw.hi[es >> p.tw.shift];
     {
         double2 v[PER];
 #pragma unroll
         for (int q = 0; q < PER; q++) {
-            const int e = threadIdx.x + q * NT;
-            if (L1 * W % NT == 0 || e < L1 * W) v[q] = p.za[(size_t)(e / W) * L2 + c0 + e % W];
+            const int e = tid + q * NT;
+            if (L1 * W % NT == 0 || e < L1 * W) v[q] = p.za[(size_t)(e / W) * L2 + colt];
         }
+        // inverse inter-pass twiddles exp(+2 pi i col k1 / M)
+        TwSeq<PER> tws;
+        tws.init(cconj(cmul(tb0, tb1)), cconj(cmul(ts0, ts1)));
 #pragma unroll
         for (int q = 0; q < PER; q++) {
-            const int e = threadIdx.x + q * NT;
-            if (L1 * W % NT == 0 || e < L1 * W) tile[e] = v[q];
+            const int e = tid + q * NT;
+            if (L1 * W % NT == 0 || e < L1 * W) tile[pidx(e)] = cmul(v[q], tws.at(q));
         }
     }
     __syncthreads();
-    tile_fft<L1, W, NT, true, true>(tile, p.tw, p.M / L1);
+    tile_fft<L1, W, NT, true, true>(tile, twl);
 #pragma unroll
     for (int q = 0; q < PER; q++) {
         const int e = threadIdx.x + q * NT;
-        if (L1 * W % NT == 0 || e < L1 * W) p.za[(size_t)(e / W) * L2 + c0 + e % W] = tile[e];
+        if (L1 * W % NT == 0 || e < L1 * W) p.za[(size_t)(e / W) * L2 + c0 + e % W] = tile[pidx(e)];
     }
 }
 
@@ -521,9 +546,12 @@ __device__ __forceinline__ double back_lo(const KParams& p, const double* sq, ui
     const uint32_t N = p.N;
     const int o = (int)((int64_t)i - (int64_t)base) + K4_HALO;
     double s = 0.0;
-    for (int r = 0; r < p.lam; r++) {
-        const uint32_t k = i >= (uint32_t)r ? i - r : i + N - r;
-        s = fma(coef_back(K_LO, k, r, p.invN, p.cb[r]), sq[o - r], s);
+#pragma unroll
+    for (int r = 0; r < LMAX; r++) {
+        if (r < p.lam) {
+            const uint32_t k = i >= (uint32_t)r ? i - r : i + N - r;
+            s = fma(coef_back(K_LO, k, r, p.invN, p.cb[r]), sq[o - r], s);
+        }
     }
     if (i >= 1 && i < (uint32_t)p.lam) {
         double t = 0.0;
@@ -539,8 +567,10 @@ __device__ __forceinline__ double back_hi(const KParams& p, const double* sq, ui
     const uint32_t N = p.N;
     const int o = (int)((int64_t)i - (int64_t)base) + K4_HALO;
     double s = 0.0;
-    for (int r = 0; r < p.lam && (uint32_t)r <= i; r++)
-        s = fma(coef_back(K_HI, i - r, r, p.invN, p.cb[r]), sq[o - r], s);
+#pragma unroll
+    for (int r = 0; r < LMAX; r++) {
+        if (r < p.lam && (uint32_t)r <= i) s = fma(coef_back(K_HI, i - r, r, p.invN, p.cb[r]), sq[o - r], s);
+    }
     if (i < (uint32_t)p.lam + p.jmax) {
         for (int j = 0; j <= (int)i && j <= (int)p.jmax; j++) {
             double t = 0.0;
@@ -814,6 +844,18 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
         const bool full = sl >= sb0 && sl + 64 <= sb1 && (uint64_t)(li + 1) * 64 <= p.out_bits;
         if (full) p.w[li] = val;
         else atomicOr(reinterpret_cast<unsigned long long*>(&p.w[li]), (unsigned long long)val);
+    }
+}
+
+// sub-transform table: t[e] = exp(-2 pi i e / P), e < P
+__global__ void k_subtwiddles(double2* t, uint32_t P)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P) {
+        const int64_t ee = i > P / 2 ? (int64_t)i - (int64_t)P : (int64_t)i;
+        double s, c;
+        sincospi(-2.0 * ((double)ee / (double)P), &s, &c);
+        t[i] = make_double2(c, s);
     }
 }
 

@@ -41,12 +41,16 @@ tm_status hip_fail(hipError_t e, const char* what)
 struct TwEntry {
     double2* buf = nullptr;
     Tw tw{};
+    const double2* sub1 = nullptr;  // exp(-2 pi i e / L1), e < L1
+    const double2* sub2 = nullptr;  // exp(-2 pi i e / L2), e < L2
 };
 
 std::mutex g_tw_mu;
 std::map<std::pair<int, uint64_t>, TwEntry> g_tw;
 
-tm_status get_twiddles(uint64_t M, hipStream_t s, Tw& out)
+// Twiddle tables for transform length M = L1 * L2 (the plan fixes L1, L2
+// from M), built once per device.
+tm_status get_twiddles(uint64_t M, uint32_t L1, uint32_t L2, hipStream_t s, TwEntry& out)
 {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -54,25 +58,29 @@ tm_status get_twiddles(uint64_t M, hipStream_t s, Tw& out)
     auto key = std::make_pair(dev, M);
     auto it = g_tw.find(key);
     if (it != g_tw.end()) {
-        out = it->second.tw;
+        out = it->second;
         return TM_OK;
     }
     uint32_t sh = (uint32_t)((lg_ceil(M) + 1) / 2);
     uint32_t S = 1u << sh;
     uint32_t nhi = (uint32_t)((M + S - 1) / S);
     TwEntry e;
-    HIP_TRY(hipMalloc(&e.buf, (size_t)(S + nhi) * sizeof(double2)));
+    HIP_TRY(hipMalloc(&e.buf, (size_t)(S + nhi + L1 + L2) * sizeof(double2)));
     uint32_t n = S > nhi ? S : nhi;
     hipLaunchKernelGGL(k_twiddles, dim3((n + 255) / 256), dim3(256), 0, s, e.buf, e.buf + S,
                        (uint32_t)M, S, nhi);
+    hipLaunchKernelGGL(k_subtwiddles, dim3((L1 + 255) / 256), dim3(256), 0, s, e.buf + S + nhi, L1);
+    hipLaunchKernelGGL(k_subtwiddles, dim3((L2 + 255) / 256), dim3(256), 0, s, e.buf + S + nhi + L1, L2);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     e.tw.lo = e.buf;
     e.tw.hi = e.buf + S;
     e.tw.shift = sh;
     e.tw.mask = S - 1;
+    e.sub1 = e.buf + S + nhi;
+    e.sub2 = e.buf + S + nhi + L1;
     g_tw[key] = e;
-    out = e.tw;
+    out = e;
     return TM_OK;
 }
 
@@ -154,7 +162,7 @@ double inv_fact(int r)
 }
 
 void fill_params(const Plan& P, const uint64_t* u, const uint64_t* v, uint64_t* w, void* ws,
-                 tm_guard* guard, const Tw& tw, KParams& p)
+                 tm_guard* guard, const TwEntry& tw, KParams& p)
 {
     memset(&p, 0, sizeof p);
     char* base = static_cast<char*>(ws);
@@ -196,7 +204,9 @@ void fill_params(const Plan& P, const uint64_t* u, const uint64_t* v, uint64_t* 
     p.ticket = reinterpret_cast<uint32_t*>(base + P.o_ticket);
     p.guard = guard ? guard : reinterpret_cast<tm_guard*>(base + P.o_guard);
     p.theta = reinterpret_cast<double*>(base + P.o_theta);
-    p.tw = tw;
+    p.tw = tw.tw;
+    p.tw1 = tw.sub1;
+    p.tw2 = tw.sub2;
 }
 
 tm_status plan_for(tm_kind kind, uint64_t n, Plan& P, int bt = 0, int bf = 0)
@@ -242,8 +252,8 @@ tm_status run(const Plan& P, uint64_t* w, const uint64_t* u, const uint64_t* v, 
         g_last_error = "workspace must be 256-byte aligned";
         return TM_ERR_INVALID;
     }
-    Tw tw;
-    tm_status st = get_twiddles(P.M, s, tw);
+    TwEntry tw;
+    tm_status st = get_twiddles(P.M, P.L1, P.L2, s, tw);
     if (st != TM_OK) return st;
     KParams p;
     uint64_t dummy_out = 0;
