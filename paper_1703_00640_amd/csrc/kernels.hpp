@@ -240,18 +240,74 @@ __device__ __forceinline__ void row_digits(const KParams& p, const uint64_t* x, 
     }
 }
 
-// G_(2m0+2c+e) for one row:
+// Window start of a row: first field at bit p0 = (kf - 1) b - shift, limb
+// l0 = floor(p0 / 64), relative offset rel0 = p0 - 64 l0.
+__device__ __forceinline__ void row_window(const KParams& p, int64_t kf, int64_t& l0, int& rel0)
+{
+    const int64_t p0 = (kf - 1) * p.b - p.shift;
+    l0 = p0 >= 0 ? p0 >> 6 : -((63 - p0) >> 6);
+    rel0 = (int)(p0 - l0 * 64);
+}
+
+// limb li of x mod 2^n (zero outside [0, L))
+__device__ __forceinline__ uint64_t limb_at(const KParams& p, const uint64_t* x, int64_t li)
+{
+    uint64_t v = (li >= 0 && li < (int64_t)p.L) ? x[li] : 0;
+    if (li == (int64_t)p.L - 1 && (p.n & 63)) v &= (1ull << (p.n & 63)) - 1;
+    return v;
+}
+
+// Digits of a row from its limb window staged in LDS (slimb = NLW limbs).
+template <int ND, int NLW, int KIND>
+__device__ __forceinline__ void row_digits_lds(const KParams& p, const uint64_t* x, int64_t kf,
+                                               const uint64_t* slimb, int32_t (&d)[ND])
+{
+    const int b = p.b;
+    const int64_t top = KIND == K_FULL ? (int64_t)p.digits - 1 : (int64_t)p.N;
+    if (KIND == K_FULL && kf > top) {
+#pragma unroll
+        for (int t = 0; t < ND; t++) d[t] = 0;
+        return;
+    }
+    const bool fast = kf >= 0 && (KIND == K_FULL ? kf + ND <= top : true);
+    if (fast) {
+        int64_t l0;
+        int rel0;
+        row_window(p, kf, l0, rel0);
+        const int64_t mask = (1ll << b) - 1, h = 1ll << (b - 1);
+#pragma unroll
+        for (int t = 0; t < ND; t++) {
+            const int rel = rel0 + t * b;
+            const int li = rel >> 6, sh = rel & 63;
+            const uint64_t lo = slimb[li], hi = slimb[li + 1];
+            const uint64_t w = sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
+            const int64_t dprev = (int64_t)(w & mask), dd = (int64_t)((w >> b) & mask);
+            d[t] = (int32_t)(dd - (dd >= h ? (1ll << b) : 0) + (dprev >= h ? 1 : 0));
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < ND; t++) {
+            int64_t k = kf + t;
+            if (KIND == K_FULL) {
+                d[t] = k <= top ? (int32_t)bal_digit(p, x, k, p.digits, true) : 0;
+            } else {
+                if (k < 0) k += p.N;
+                d[t] = (int32_t)bal_digit(p, x, k, p.digits, false);
+            }
+        }
+    }
+}
+
+// G_(2m0+2c+e) for one row from its digits d (d[t] = digit 2 m0 - LO + t):
 //   full: the digits themselves;
 //   low:  G = alpha* U   (Prop. approximating alpha*), cyclic indices;
 //   high: G = gamma* F'  with F'_k = F_k + 2^(-kb) F_N  (F mod C by eq.
 //         reduction-modC with rho ~ 2^b, Prop. approximating gamma-dagger).
-template <int W, int KIND>
-__device__ __forceinline__ void row_values(const KParams& p, const uint64_t* x, uint32_t m0,
-                                           double FN, double2 (&g)[W])
+template <int W, int KIND, int ND>
+__device__ __forceinline__ void row_map(const KParams& p, uint32_t m0, double FN,
+                                        const int32_t (&d)[ND], double2* g)
 {
-    constexpr int ND = k1_nd(W, KIND), LO = k1_lo(KIND);
-    int32_t d[ND];
-    row_digits<ND, KIND>(p, x, 2 * (int64_t)m0 - LO, d);
+    constexpr int LO = k1_lo(KIND);
     if constexpr (KIND == K_FULL) {
 #pragma unroll
         for (int c = 0; c < W; c++) g[c] = make_double2((double)d[2 * c], (double)d[2 * c + 1]);
@@ -283,7 +339,12 @@ __global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
 {
     static_assert(L1 * W <= TILE, "tile too large");
     constexpr int PER = (L1 * W + NT - 1) / NT;
-    __shared__ double2 tile[padded(L1 * W)];
+    constexpr int ND = k1_nd(W, KIND), LO = k1_lo(KIND), NLW = k1_nlw(ND);
+    constexpr int TE = padded(L1 * W);
+    // limb windows staged in the tile area when they fit
+    constexpr bool STAGE = L1 * NLW * 8 <= TE * 16;
+    constexpr int RPT = (L1 + NT - 1) / NT;
+    __shared__ double2 tile[TE];
     __shared__ double2 twl[twl_size(L1)];
     __shared__ double s_FN;
     const int op = blockIdx.y;
@@ -306,14 +367,52 @@ __global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
         s_FN = (double)bal_digit(p, x, p.N, p.digits, true);
         if (blockIdx.x == 0) p.theta[op] = hi_theta(p, x);
     }
+    if constexpr (STAGE) {
+        uint64_t* slimb = reinterpret_cast<uint64_t*>(tile);
+        constexpr int PL = (L1 * NLW + NT - 1) / NT;
+        uint64_t lv[PL];
+#pragma unroll
+        for (int q = 0; q < PL; q++) {
+            const int e = tid + q * NT;
+            if (L1 * NLW % NT == 0 || e < L1 * NLW) {
+                const int row = e / NLW, i = e % NLW;
+                int64_t l0;
+                int rel0;
+                row_window(p, 2 * ((int64_t)row * L2 + c0) - LO, l0, rel0);
+                lv[q] = limb_at(p, x, l0 + i);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PL; q++) {
+            const int e = tid + q * NT;
+            if (L1 * NLW % NT == 0 || e < L1 * NLW) slimb[e] = lv[q];
+        }
+    }
     __syncthreads();
     const double FN = KIND == K_HI ? s_FN : 0.0;
-    // one row (W complex points) per thread
-    for (int j1 = tid; j1 < L1; j1 += NT) {
-        double2 g[W];
-        row_values<W, KIND>(p, x, (uint32_t)j1 * L2 + c0, FN, g);
+    double2 g[RPT][W];
 #pragma unroll
-        for (int c = 0; c < W; c++) tile[pidx(j1 * W + c)] = g[c];
+    for (int rr = 0; rr < RPT; rr++) {
+        const int j1 = tid + rr * NT;
+        if (L1 % NT == 0 || j1 < L1) {
+            const uint32_t m0 = (uint32_t)j1 * L2 + c0;
+            int32_t d[ND];
+            if constexpr (STAGE)
+                row_digits_lds<ND, NLW, KIND>(p, x, 2 * (int64_t)m0 - LO,
+                                              reinterpret_cast<const uint64_t*>(tile) + j1 * NLW, d);
+            else
+                row_digits<ND, KIND>(p, x, 2 * (int64_t)m0 - LO, d);
+            row_map<W, KIND, ND>(p, m0, FN, d, g[rr]);
+        }
+    }
+    if constexpr (STAGE) __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < RPT; rr++) {
+        const int j1 = tid + rr * NT;
+        if (L1 % NT == 0 || j1 < L1) {
+#pragma unroll
+            for (int c = 0; c < W; c++) tile[pidx(j1 * W + c)] = g[rr][c];
+        }
     }
     __syncthreads();
     tile_fft<L1, W, NT, false, true>(tile, twl);
@@ -562,23 +661,34 @@ __device__ __forceinline__ double back_lo(const KParams& p, const double* sq, ui
     return s;
 }
 
-__device__ __forceinline__ double back_hi(const KParams& p, const double* sq, uint64_t base, uint32_t i)
+// Wrapped part of H_i (i < lam + jmax, workgroup 0 only):
+// sum_j 2^(-jb) sum_{r > i-j} delta_{N+i-j-r,r} W_(N+i-j-r).
+__device__ double back_hi_wrap(const KParams& p, const double* sq, uint32_t i)
 {
     const uint32_t N = p.N;
+    const int o = (int)i + K4_HALO;
+    double s = 0.0;
+    for (int j = 0; j <= (int)i && j <= (int)p.jmax; j++) {
+        double t = 0.0;
+        for (int r = (int)i - j + 1; r < p.lam; r++)
+            t = fma(coef_back(K_HI, N + i - j - r, r, p.invN, p.cb[r]), sq[o - j - r], t);
+        s = fma(ldexp(1.0, -j * p.b), t, s);
+    }
+    return s;
+}
+
+// H_i: the unwrapped terms, plus the precomputed wrapped part swrap[i]
+// for i < K4_HALO in workgroup 0.
+__device__ __forceinline__ double back_hi(const KParams& p, const double* sq, const double* swrap,
+                                          uint64_t base, uint32_t i)
+{
     const int o = (int)((int64_t)i - (int64_t)base) + K4_HALO;
     double s = 0.0;
 #pragma unroll
     for (int r = 0; r < LMAX; r++) {
         if (r < p.lam && (uint32_t)r <= i) s = fma(coef_back(K_HI, i - r, r, p.invN, p.cb[r]), sq[o - r], s);
     }
-    if (i < (uint32_t)p.lam + p.jmax) {
-        for (int j = 0; j <= (int)i && j <= (int)p.jmax; j++) {
-            double t = 0.0;
-            for (int r = (int)i - j + 1; r < p.lam; r++)
-                t = fma(coef_back(K_HI, N + i - j - r, r, p.invN, p.cb[r]), sq[o - j - r], t);
-            s = fma(ldexp(1.0, -j * p.b), t, s);
-        }
-    }
+    if (i < (uint32_t)K4_HALO) s += swrap[i];
     return s;
 }
 
@@ -593,6 +703,7 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
     __shared__ int64_t sWA[NW], sWT[NW];
     __shared__ double sGD[NW], sGA[NW];
     __shared__ uint32_t sGF;
+    __shared__ double swrap[K4_HALO];
     uint16_t* sd = reinterpret_cast<uint16_t*>(sq);  // digits reuse the q staging area
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const double* q = reinterpret_cast<const double*>(p.za);
@@ -629,15 +740,21 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
             xv[t] = i < p.ncoef ? ldexp(back_lo(p, sq, base, (uint32_t)i) * p.invM, b) : 0.0;
         }
     } else {
+        // wrapped terms of H (workgroup 0), one thread per index
+        if (base == 0) {
+            if (tid < K4_HALO)
+                swrap[tid] = (uint32_t)tid < (uint32_t)p.lam + p.jmax ? back_hi_wrap(p, sq, tid) : 0.0;
+            __syncthreads();
+        }
         // H for i0-1 .. i0+DPT-1, then J_i = (H_i - 2^-b H_(i-1)) / M - theta_W 2^(-ib)
         const double eps = ldexp(1.0, -b);
-        double hprev = (i0 >= 1 && i0 - 1 < p.N) ? back_hi(p, sq, base, (uint32_t)(i0 - 1)) : 0.0;
+        double hprev = (i0 >= 1 && i0 - 1 < p.N) ? back_hi(p, sq, swrap, base, (uint32_t)(i0 - 1)) : 0.0;
 #pragma unroll
         for (int t = 0; t < DPT; t++) {
             const uint64_t i = i0 + t;
             if (i >= p.ncoef) { xv[t] = 0.0; continue; }
             if (i < p.N) {
-                const double h = back_hi(p, sq, base, (uint32_t)i);
+                const double h = back_hi(p, sq, swrap, base, (uint32_t)i);
                 xv[t] = ldexp(fma(-eps, hprev, h) * p.invM - ldexp(thW, -(int)i * b), b);
                 hprev = h;
             } else {
