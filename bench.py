@@ -43,6 +43,60 @@ def kernel_bytes(plan, n_bits, kind):
             "backmap_round_carry": 8 * N + out}
 
 
+def source_hash():
+    """sha1 of the HIP sources and the C header (ties stored counter figures
+    to the kernels they were taken on)."""
+    import hashlib
+    h = hashlib.sha1()
+    csrc = os.path.join(ROOT, "paper_1703_00640_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc)) + [
+        os.path.join(ROOT, "include", "tmul.h")]
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(log2n):
+    """HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
+    (profiles/traffic_n2_<log2n>.txt), keyed by kind:kernel, or {} when the
+    file is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_n2_%d.txt" % log2n)
+    if not os.path.exists(path):
+        return {}
+    out, src = {}, None
+    for line in open(path):
+        f = line.split()
+        if len(f) == 2 and f[0] == "source_hash:":
+            src = f[1]
+        elif len(f) == 4 and f[0] == "traffic:":
+            out[f[1]] = int(f[2]) + int(f[3])
+    return out if src == source_hash() else {}
+
+
+def pmc_pass(n_bits):
+    """Workload for rocprofv3 counter passes: each product twice, then a
+    plain 256 MiB device copy (the calibration kernel for FETCH_SIZE and
+    WRITE_SIZE)."""
+    import torch
+    import paper_1703_00640_amd as tm
+    from paper_1703_00640_amd import inputs
+    dev = torch.device("cuda:0")
+    u, v = inputs.operand_pair(n_bits, 2)
+    du = torch.from_numpy(u.view(np.int64)).to(dev)
+    dv = torch.from_numpy(v.view(np.int64)).to(dev)
+    for k in ("lo", "hi", "full"):
+        ws = torch.empty(tm.plan(k, n_bits)["workspace_bytes"], dtype=torch.uint8, device=dev)
+        for _ in range(2):
+            tm.mul(k, du, dv, n_bits, workspace=ws)
+    a = torch.ones(1 << 25, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("pmc pass done", flush=True)
+
+
 def cpu_baseline(n_bits, threads):
     import oracle
     from paper_1703_00640_amd import inputs
@@ -64,7 +118,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="run the counter-collection workload instead of the benchmark")
     args = ap.parse_args()
+    if args.pmc_pass:
+        pmc_pass(1 << args.log2n)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how it would shard)", file=sys.stderr)
@@ -138,6 +197,9 @@ def main():
                 best = (k, name, ms, nb[name])
     k_dom, name_dom, ms_dom, bytes_dom = best
     achieved = bytes_dom / (ms_dom * 1e-3) / 1e9
+    traffic = stored_traffic(args.log2n).get("%s:%s" % (k_dom, name_dom))
+    stage_gbs = {k: {nm: round(kernel_bytes(plans[k], n, k)[nm] / (t * 1e-3) / 1e9, 1)
+                     for nm, t in stage[k].items()} for k in kinds}
 
     gd = {k: tm.read_guard(guards[k]).as_dict() for k in kinds}
     result = {
@@ -166,8 +228,10 @@ def main():
         "guard_flags": {k: gd[k]["flags"] for k in kinds},
         "roofline": {"bound": "hbm", "kernel": "%s:%s" % (k_dom, name_dom),
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": bytes_dom, "ms_per_launch": round(ms_dom, 5)},
+        "stage_gb_s": stage_gbs,
+        "source_hash": source_hash(),
         "wall_s_timed": round(wall, 3),
     }
     if not args.no_cpu:
