@@ -172,6 +172,16 @@ __device__ __forceinline__ void clear_state(const KParams& p, uint32_t gid, uint
 
 // ------------------------------------------------------------------- K1
 
+// Column tiles c and c+1 share 128-byte lines (W complex doubles = 16 W
+// bytes per row segment).  Workgroups are dispatched round-robin over the 8
+// XCDs, each with its own L2; map workgroup id -> tile so that consecutive
+// tiles run on the same XCD and a line is fetched once.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t ntiles)
+{
+    if (ntiles % 8 != 0) return bid;
+    return (bid % 8) * (ntiles / 8) + bid / 8;
+}
+
 // Digits of one K1 tile row.  A row holds complex points m0 .. m0+W-1, i.e.
 // reals 2 m0 .. 2 m0 + 2W - 1; the truncated products' stencil also reads
 // the LMAX - 1 digits below.  The row's limbs are fetched once (independent
@@ -351,7 +361,7 @@ __global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
     const uint64_t* x = op ? p.v : p.u;
     double2* dst = op ? p.zb : p.za;
     const uint32_t L2 = p.L2;
-    const uint32_t c0 = blockIdx.x * W;
+    const uint32_t c0 = xcd_tile(blockIdx.x, gridDim.x) * W;
     const int tid = threadIdx.x;
 
     load_twl<L1, NT>(twl, p.tw1);
@@ -531,7 +541,7 @@ __global__ __launch_bounds__(NT) void k3_col_inverse(KParams p)
     __shared__ double2 tile[padded(L1 * W)];
     __shared__ double2 twl[twl_size(L1)];
     const uint32_t L2 = p.L2;
-    const uint32_t c0 = blockIdx.x * W;
+    const uint32_t c0 = xcd_tile(blockIdx.x, gridDim.x) * W;
     load_twl<L1, NT>(twl, p.tw1);
     constexpr int PER = (L1 * W + NT - 1) / NT;
     static_assert(NT % W == 0, "W must divide NT");
