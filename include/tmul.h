@@ -91,8 +91,10 @@ typedef struct {
     uint64_t digits;        /* digits per operand: N (low), N+1 (high), N (full,
                                paper notation)                                    */
     uint64_t M;             /* complex FFT length = N/2                           */
-    uint32_t L1, L2;        /* M = L1 * L2: column and row sub-transform lengths  */
+    uint32_t L1, L2;        /* M = L1 * Lm * L2: column and row sub-transform     */
     uint64_t workspace_bytes;
+    uint32_t Lm;            /* middle sub-transform length (1: two-pass FFT)      */
+    uint32_t reserved;
 } tm_plan_info;
 
 /* One request of a batch: w = product(kind, u, v) on n_bits-bit operands. */
@@ -179,10 +181,11 @@ tm_status tm_coefficients(tm_kind kind, int64_t* coeffs, double* x, uint64_t coe
 /*
  * Measurement: run one multiplication with HIP events recorded on `stream`
  * between its kernels, synchronise, and write the elapsed milliseconds of
- * each kernel to stage_ms[0..*n_stages) (capacity `cap`) and their names to
- * names[i] (static strings; may be NULL).  The stages are: split+map+column
- * FFT, row FFT+pointwise+inverse row FFT, inverse column FFT,
- * back-map+round+carry.
+ * each kernel to stage_ms[0..*n_stages) (capacity `cap`, at least 6) and
+ * their names to names[i] (static strings; may be NULL).  The stages are:
+ * split+map+column FFT, [middle column FFT,] row FFT+pointwise+inverse row
+ * FFT, [inverse middle column FFT,] inverse column FFT, back-map+round+carry
+ * (the bracketed ones only for the three-pass split, plan Lm > 1).
  */
 tm_status tm_profile_stages(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v,
                             uint64_t n_bits, void* workspace, size_t workspace_bytes,

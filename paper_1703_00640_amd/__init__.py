@@ -45,7 +45,8 @@ class _PlanInfo(ctypes.Structure):
                 ("n_bits", ctypes.c_uint64), ("N", ctypes.c_uint64),
                 ("digits", ctypes.c_uint64), ("M", ctypes.c_uint64),
                 ("L1", ctypes.c_uint32), ("L2", ctypes.c_uint32),
-                ("workspace_bytes", ctypes.c_uint64)]
+                ("workspace_bytes", ctypes.c_uint64), ("Lm", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class _Request(ctypes.Structure):

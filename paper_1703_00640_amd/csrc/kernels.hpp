@@ -45,7 +45,8 @@ struct KParams {
     int32_t lam;        // series length (truncated products)
     uint32_t N;         // real convolution length
     uint32_t digits;    // digits per operand (low: N, high: N+1, full: N/2)
-    uint32_t M, L1, L2; // complex length and its split
+    uint32_t M, L1, L2; // complex length and its split M = L1 * Lm * L2
+    uint32_t Lm, R;     // middle pass length (1: two-pass) and row length R = Lm * L2
     uint32_t jmax;      // powers 2^-jb kept in the high-product wrap terms
     int64_t shift;      // high product: s = (N+1) b - n
     uint64_t off;       // output = bits [off, off+out_bits) of S
@@ -67,6 +68,7 @@ struct KParams {
     Tw tw;
     const double2* tw1; // exp(-2 pi i e / L1), e < L1
     const double2* tw2; // exp(-2 pi i e / L2), e < L2
+    const double2* twm; // exp(-2 pi i e / Lm), e < Lm
     int64_t* dbg_c;     // diagnostic outputs (tm_coefficients) or null
     double* dbg_x;
 };
@@ -360,7 +362,7 @@ __global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
     const int op = blockIdx.y;
     const uint64_t* x = op ? p.v : p.u;
     double2* dst = op ? p.zb : p.za;
-    const uint32_t L2 = p.L2;
+    const uint32_t L2 = p.R;  // row length of the L1 x R matrix
     const uint32_t c0 = xcd_tile(blockIdx.x, gridDim.x) * W;
     const int tid = threadIdx.x;
 
@@ -369,7 +371,8 @@ __global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
     // share col = c0 + tid % W and step k1 by NT / W
     static_assert(NT % W == 0, "W must divide NT");
     const uint32_t colt = c0 + tid % W;
-    const uint32_t eb = (colt * (uint32_t)(tid / W)) % p.M, es = (colt * (uint32_t)(NT / W)) % p.M;
+    const uint32_t eb = (uint32_t)((uint64_t)colt * (uint32_t)(tid / W) % p.M);
+    const uint32_t es = (uint32_t)((uint64_t)colt * (uint32_t)(NT / W) % p.M);
     const double2 tb0 = p.tw.lo[eb & p.tw.mask], tb1 = p.tw.hi[eb >> p.tw.shift];
     const double2 ts0 = p.tw.lo[es & p.tw.mask], ts1 = p.tw.hi[es >> p.tw.shift];
     if (op == 0) clear_state(p, blockIdx.x * NT + tid, gridDim.x * NT);
@@ -461,20 +464,55 @@ __device__ __forceinline__ double2 pointwise_bin(double2 Ya, double2 Yam, double
     return make_double2(X.x - Yv.y, X.y + Yv.x);  // X + i Yv
 }
 
+// Row pairs of K2.  Row (k1, km) (k1 < L1, km < Lm) holds bins
+// k = k1 + L1 (km + Lm k2), k2 < L2, at positions ((k1 Lm + km) L2 + k2).
+// The mirror bin M - k lies in row (L1 - k1, Lm - 1 - km) at L2 - 1 - k2 when
+// k1 != 0, in row (0, Lm - km) at L2 - 1 - k2 when k1 = 0 and km != 0, and
+// row (0, 0) is its own mirror with k2 -> (L2 - k2) mod L2.  Workgroup g
+// takes the g-th row whose index does not exceed its mirror's.
+__host__ __device__ inline uint32_t k2_groups(uint32_t L1, uint32_t Lm)
+{
+    const uint32_t A = (L1 - 1) / 2 * Lm;
+    const uint32_t B = L1 % 2 == 0 ? (Lm + 1) / 2 : 0;
+    return A + B + Lm / 2 + 1;
+}
+
+__device__ __forceinline__ void k2_rows_of(uint32_t g, uint32_t L1, uint32_t Lm, uint32_t& k1,
+                                           uint32_t& km)
+{
+    const uint32_t A = (L1 - 1) / 2 * Lm;
+    const uint32_t B = L1 % 2 == 0 ? (Lm + 1) / 2 : 0;
+    if (g < A) {
+        k1 = 1 + g / Lm;
+        km = g % Lm;
+    } else if (g < A + B) {
+        k1 = L1 / 2;
+        km = g - A;
+    } else {
+        k1 = 0;
+        km = g - A - B;
+    }
+}
+
 template <int L2>
 __global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
 {
-    // rows 0,1: operands u,v at row k1; rows 2,3: at the mirror row
+    // rows 0,1: operands u,v at row (k1, km); rows 2,3: at the mirror row
     __shared__ double2 rows[padded(4 * L2)];
     __shared__ double2 twl[twl_size(L2)];
-    const uint32_t L1 = p.L1;
-    const uint32_t k1 = blockIdx.x;
-    const uint32_t k1m = (L1 - k1) % L1;
+    const uint32_t L1 = p.L1, Lm = p.Lm;
+    uint32_t k1, km;
+    k2_rows_of(blockIdx.x, L1, Lm, k1, km);
+    const uint32_t k1m = k1 ? L1 - k1 : 0;
+    const uint32_t kmm = k1 ? Lm - 1 - km : (km ? Lm - km : 0);
+    const uint32_t rowa = k1 * Lm + km, rowb = k1m * Lm + kmm;
+    const bool zero_row = k1 == 0 && km == 0;
     load_twl<L2, NT>(twl, p.tw2);
-    // exp(-2 pi i k / M) for bin k = rho + L1 k2 is exp(-2 pi i rho / M) times
-    // exp(-2 pi i k2 / L2): one global-table value per row
-    const double2 wr0a = p.tw.lo[k1 & p.tw.mask], wr0b = p.tw.hi[k1 >> p.tw.shift];
-    const double2 wr1a = p.tw.lo[k1m & p.tw.mask], wr1b = p.tw.hi[k1m >> p.tw.shift];
+    // exp(-2 pi i k / M) for bin k = rho + L1 Lm k2 (rho = k1 + L1 km) is
+    // exp(-2 pi i rho / M) times exp(-2 pi i k2 / L2): one table value per row
+    const uint32_t rhoa = k1 + L1 * km, rhob = k1m + L1 * kmm;
+    const double2 wr0a = p.tw.lo[rhoa & p.tw.mask], wr0b = p.tw.hi[rhoa >> p.tw.shift];
+    const double2 wr1a = p.tw.lo[rhob & p.tw.mask], wr1b = p.tw.hi[rhob >> p.tw.shift];
     {
         constexpr int PL = (4 * L2 + NT - 1) / NT;
         double2 v[PL];
@@ -483,7 +521,7 @@ __global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
             const int e = threadIdx.x + q * NT;
             if (4 * L2 % NT == 0 || e < 4 * L2) {
                 const int r = e / L2, j2 = e % L2;
-                const uint32_t row = r < 2 ? k1 : k1m;
+                const uint32_t row = r < 2 ? rowa : rowb;
                 const double2* src = (r & 1) ? p.zb : p.za;
                 v[q] = src[(size_t)row * L2 + j2];
             }
@@ -505,8 +543,7 @@ __global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
         const int e = threadIdx.x + t * NT;
         if (e < 2 * L2) {
             const int pr = e / L2, k2 = e % L2;
-            const uint32_t rho = pr ? k1m : k1;
-            const int mk2 = rho == 0 ? (L2 - k2) % L2 : L2 - 1 - k2;
+            const int mk2 = zero_row ? (L2 - k2) % L2 : L2 - 1 - k2;
             const int mr = 1 - pr;
             qv[t] = pointwise_bin(rows[pidx((2 * pr) * L2 + k2)], rows[pidx((2 * mr) * L2 + mk2)],
                                   rows[pidx((2 * pr + 1) * L2 + k2)], rows[pidx((2 * mr + 1) * L2 + mk2)],
@@ -527,9 +564,59 @@ __global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
     tile_fft<L2, 2, NT, true, false, 2 * L2>(rows, twl);
     for (int e = threadIdx.x; e < 2 * L2; e += NT) {
         const int pr = e / L2, j2 = e % L2;
-        if (pr == 1 && k1m == k1) continue;
-        const uint32_t rho = pr ? k1m : k1;
-        p.za[(size_t)rho * L2 + j2] = rows[pidx((2 * pr) * L2 + j2)];
+        if (pr == 1 && rowb == rowa) continue;
+        p.za[(size_t)(pr ? rowb : rowa) * L2 + j2] = rows[pidx((2 * pr) * L2 + j2)];
+    }
+}
+
+// ------------------------------------------------------------ middle pass
+
+// Middle column pass of the three-pass split (Lm > 1): inside each row k1
+// of the L1 x R matrix (R = Lm L2), Lm-point DFTs over jm (stride L2) for W
+// adjacent columns j2.  Forward: DFT, then exp(-2 pi i j2 km / R), in place
+// on both operands.  Inverse: exp(+2 pi i j2 km / R), then inverse DFT, on
+// the product.  grid = (L2 / W, L1, operands).
+template <int LM, int W, bool INV>
+__global__ __launch_bounds__(NT) void k_mid_col(KParams p)
+{
+    constexpr int PER = (LM * W + NT - 1) / NT;
+    static_assert(NT % W == 0, "W must divide NT");
+    __shared__ double2 tile[padded(LM * W)];
+    __shared__ double2 twl[twl_size(LM)];
+    const uint32_t L2 = p.L2;
+    const uint32_t c0 = xcd_tile(blockIdx.x, gridDim.x) * W;
+    double2* a = (blockIdx.z ? p.zb : p.za) + (size_t)blockIdx.y * p.R;
+    const int tid = threadIdx.x;
+    load_twl<LM, NT>(twl, p.twm);
+    // twiddle exponents on the R-th root, as exponents of the M-th root (x L1)
+    const uint32_t colt = c0 + tid % W;
+    const uint32_t eb = (uint32_t)(((uint64_t)colt * (uint32_t)(tid / W) * p.L1) % p.M);
+    const uint32_t es = (uint32_t)(((uint64_t)colt * (uint32_t)(NT / W) * p.L1) % p.M);
+    const double2 tb0 = p.tw.lo[eb & p.tw.mask], tb1 = p.tw.hi[eb >> p.tw.shift];
+    const double2 ts0 = p.tw.lo[es & p.tw.mask], ts1 = p.tw.hi[es >> p.tw.shift];
+    double2 v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int e = tid + q * NT;
+        if (LM * W % NT == 0 || e < LM * W) v[q] = a[(size_t)(e / W) * L2 + colt];
+    }
+    TwSeq<PER> tws;
+    if (INV) tws.init(cconj(cmul(tb0, tb1)), cconj(cmul(ts0, ts1)));
+    else tws.init(cmul(tb0, tb1), cmul(ts0, ts1));
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int e = tid + q * NT;
+        if (LM * W % NT == 0 || e < LM * W) tile[pidx(e)] = INV ? cmul(v[q], tws.at(q)) : v[q];
+    }
+    __syncthreads();
+    tile_fft<LM, W, NT, INV, true>(tile, twl);
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int e = tid + q * NT;
+        if (LM * W % NT == 0 || e < LM * W) {
+            const double2 t = tile[pidx(e)];
+            a[(size_t)(e / W) * L2 + colt] = INV ? t : cmul(t, tws.at(q));
+        }
     }
 }
 
@@ -540,14 +627,15 @@ __global__ __launch_bounds__(NT) void k3_col_inverse(KParams p)
 {
     __shared__ double2 tile[padded(L1 * W)];
     __shared__ double2 twl[twl_size(L1)];
-    const uint32_t L2 = p.L2;
+    const uint32_t L2 = p.R;  // row length of the L1 x R matrix
     const uint32_t c0 = xcd_tile(blockIdx.x, gridDim.x) * W;
     load_twl<L1, NT>(twl, p.tw1);
     constexpr int PER = (L1 * W + NT - 1) / NT;
     static_assert(NT % W == 0, "W must divide NT");
     const int tid = threadIdx.x;
     const uint32_t colt = c0 + tid % W;
-    const uint32_t eb = (colt * (uint32_t)(tid / W)) % p.M, es = (colt * (uint32_t)(NT / W)) % p.M;
+    const uint32_t eb = (uint32_t)((uint64_t)colt * (uint32_t)(tid / W) % p.M);
+    const uint32_t es = (uint32_t)((uint64_t)colt * (uint32_t)(NT / W) % p.M);
     const double2 tb0 = p.tw.lo[eb & p.tw.mask], tb1 = p.tw.hi[eb >> p.tw.shift];
     const double2 ts0 = p.tw.lo[es & p.tw.mask], ts1 = p.tw.hi[es >> p.tw.shift];
     {

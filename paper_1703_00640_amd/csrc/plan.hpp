@@ -18,7 +18,7 @@ namespace tmul {
 constexpr int B_TRUNC = 11;          // digit size of the truncated products (8..15)
 constexpr int B_FULL = 16;           // digit size of the full product
 constexpr uint64_t TRUNC_MIN_BITS = 1025;  // below: full product + extraction
-constexpr uint32_t L2_MAX = 1024, L1_MAX = 4096;
+constexpr uint32_t L2_MAX = 1024, L1_MAX = 4096, LM_MAX = 256;
 constexpr int DPW_HOST = 7 * 1024;   // digits per K4 workgroup
 
 struct Plan {
@@ -30,7 +30,7 @@ struct Plan {
     uint64_t N = 0;       // real convolution length
     uint64_t digits = 0;  // digits per operand
     uint64_t M = 0;
-    uint32_t L1 = 0, L2 = 0;
+    uint32_t L1 = 0, L2 = 0, Lm = 1;  // M = L1 * Lm * L2
     uint32_t jmax = 0;
     int64_t shift = 0;
     uint64_t off = 0, out_bits = 0, out_limbs = 0;
@@ -72,6 +72,22 @@ inline bool split_M(uint64_t M, uint32_t& L1, uint32_t& L2)
     return true;
 }
 
+// M = L1 * Lm * L2: the smallest power of two Lm (the middle pass of the
+// three-pass split; 1 = two passes) that keeps the column length L1 <= 1024,
+// or the forced Lm.
+inline bool split_M3(uint64_t M, uint32_t force_lm, uint32_t& L1, uint32_t& Lm, uint32_t& L2)
+{
+    if (force_lm > 1) {
+        Lm = force_lm;
+        return (Lm & (Lm - 1)) == 0 && Lm <= LM_MAX && M % Lm == 0 && split_M(M / Lm, L1, L2);
+    }
+    for (Lm = 1; Lm <= LM_MAX; Lm *= 2) {
+        if (M % Lm != 0) return false;
+        if (split_M(M / Lm, L1, L2) && L1 <= 1024) return true;
+    }
+    return false;
+}
+
 // smallest N in {2^a, 3*2^a}, N >= max(x, 64)
 inline uint64_t next_smooth(uint64_t x)
 {
@@ -89,7 +105,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Build the plan.  b_trunc / b_full: digit sizes (0 = default).
 // Returns false if unsupported.
-inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P)
+inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P, uint32_t force_lm = 0)
 {
     if (n == 0 || kind < 0 || kind > 2) return false;
     P = Plan();
@@ -140,7 +156,7 @@ inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P)
         P.out_limbs = P.L;
     }
     P.M = P.N / 2;
-    if (!split_M(P.M, P.L1, P.L2)) return false;
+    if (!split_M3(P.M, force_lm, P.L1, P.Lm, P.L2)) return false;
     uint64_t need = (P.off + P.out_bits + P.b - 1) / P.b + 2;
     uint64_t cov = P.ncoef > need ? P.ncoef : need;
     P.ncover = (cov + DPW_HOST - 1) / DPW_HOST * DPW_HOST;

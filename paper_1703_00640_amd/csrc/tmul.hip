@@ -43,6 +43,7 @@ struct TwEntry {
     Tw tw{};
     const double2* sub1 = nullptr;  // exp(-2 pi i e / L1), e < L1
     const double2* sub2 = nullptr;  // exp(-2 pi i e / L2), e < L2
+    const double2* subm = nullptr;  // exp(-2 pi i e / Lm), e < Lm
 };
 
 std::mutex g_tw_mu;
@@ -50,12 +51,12 @@ std::map<std::pair<int, uint64_t>, TwEntry> g_tw;
 
 // Twiddle tables for transform length M = L1 * L2 (the plan fixes L1, L2
 // from M), built once per device.
-tm_status get_twiddles(uint64_t M, uint32_t L1, uint32_t L2, hipStream_t s, TwEntry& out)
+tm_status get_twiddles(uint64_t M, uint32_t L1, uint32_t Lm, uint32_t L2, hipStream_t s, TwEntry& out)
 {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_tw_mu);
-    auto key = std::make_pair(dev, M);
+    auto key = std::make_pair(dev, M * 512 + Lm);
     auto it = g_tw.find(key);
     if (it != g_tw.end()) {
         out = it->second;
@@ -65,12 +66,13 @@ tm_status get_twiddles(uint64_t M, uint32_t L1, uint32_t L2, hipStream_t s, TwEn
     uint32_t S = 1u << sh;
     uint32_t nhi = (uint32_t)((M + S - 1) / S);
     TwEntry e;
-    HIP_TRY(hipMalloc(&e.buf, (size_t)(S + nhi + L1 + L2) * sizeof(double2)));
+    HIP_TRY(hipMalloc(&e.buf, (size_t)(S + nhi + L1 + L2 + Lm) * sizeof(double2)));
     uint32_t n = S > nhi ? S : nhi;
     hipLaunchKernelGGL(k_twiddles, dim3((n + 255) / 256), dim3(256), 0, s, e.buf, e.buf + S,
                        (uint32_t)M, S, nhi);
     hipLaunchKernelGGL(k_subtwiddles, dim3((L1 + 255) / 256), dim3(256), 0, s, e.buf + S + nhi, L1);
     hipLaunchKernelGGL(k_subtwiddles, dim3((L2 + 255) / 256), dim3(256), 0, s, e.buf + S + nhi + L1, L2);
+    hipLaunchKernelGGL(k_subtwiddles, dim3((Lm + 255) / 256), dim3(256), 0, s, e.buf + S + nhi + L1 + L2, Lm);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     e.tw.lo = e.buf;
@@ -79,6 +81,7 @@ tm_status get_twiddles(uint64_t M, uint32_t L1, uint32_t L2, hipStream_t s, TwEn
     e.tw.mask = S - 1;
     e.sub1 = e.buf + S + nhi;
     e.sub2 = e.buf + S + nhi + L1;
+    e.subm = e.buf + S + nhi + L1 + L2;
     g_tw[key] = e;
     out = e;
     return TM_OK;
@@ -103,7 +106,7 @@ bool launch_k1(uint32_t L1, const KParams& p, hipStream_t s)
 {
     switch (L1) {
 #define X(V) \
-    case V: hipLaunchKernelGGL((k1_split_map_col<V, w_for(V), KIND>), dim3(p.L2 / w_for(V), 2), dim3(NT), 0, s, p); return true;
+    case V: hipLaunchKernelGGL((k1_split_map_col<V, w_for(V), KIND>), dim3(p.R / w_for(V), 2), dim3(NT), 0, s, p); return true;
         TM_L1_LIST(X)
 #undef X
     }
@@ -114,7 +117,7 @@ bool launch_k3(uint32_t L1, const KParams& p, hipStream_t s)
 {
     switch (L1) {
 #define X(V) \
-    case V: hipLaunchKernelGGL((k3_col_inverse<V, w_for(V)>), dim3(p.L2 / w_for(V)), dim3(NT), 0, s, p); return true;
+    case V: hipLaunchKernelGGL((k3_col_inverse<V, w_for(V)>), dim3(p.R / w_for(V)), dim3(NT), 0, s, p); return true;
         TM_L1_LIST(X)
 #undef X
     }
@@ -123,7 +126,7 @@ bool launch_k3(uint32_t L1, const KParams& p, hipStream_t s)
 
 bool launch_k2(uint32_t L2, const KParams& p, hipStream_t s)
 {
-    dim3 g(p.L1 / 2 + 1);
+    dim3 g(k2_groups(p.L1, p.Lm));
     switch (L2) {
     case 16: hipLaunchKernelGGL((k2_rows_pointwise<16>), g, dim3(NT), 0, s, p); return true;
     case 32: hipLaunchKernelGGL((k2_rows_pointwise<32>), g, dim3(NT), 0, s, p); return true;
@@ -133,6 +136,22 @@ bool launch_k2(uint32_t L2, const KParams& p, hipStream_t s)
     case 512: hipLaunchKernelGGL((k2_rows_pointwise<512>), g, dim3(NT), 0, s, p); return true;
     case 1024: hipLaunchKernelGGL((k2_rows_pointwise<1024>), g, dim3(NT), 0, s, p); return true;
     }
+    return false;
+}
+
+constexpr int w_mid(int LM) { return 4096 / LM < 64 ? 4096 / LM : 64; }
+
+template <bool INV>
+bool launch_mid(const KParams& p, hipStream_t s)
+{
+    const int W = (int)p.L2 < w_mid((int)p.Lm) ? (int)p.L2 : w_mid((int)p.Lm);
+    dim3 g(p.L2 / W, p.L1, INV ? 1 : 2);
+#define MIDW(LM, WW) \
+    if (p.Lm == LM && W == WW) { hipLaunchKernelGGL((k_mid_col<LM, WW, INV>), g, dim3(NT), 0, s, p); return true; }
+#define MID(LM) MIDW(LM, 16) MIDW(LM, 32) MIDW(LM, 64)
+    MID(2) MID(4) MID(8) MID(16) MID(32) MID(64) MIDW(128, 16) MIDW(128, 32) MIDW(256, 16)
+#undef MID
+#undef MIDW
     return false;
 }
 
@@ -178,6 +197,8 @@ void fill_params(const Plan& P, const uint64_t* u, const uint64_t* v, uint64_t* 
     p.M = (uint32_t)P.M;
     p.L1 = P.L1;
     p.L2 = P.L2;
+    p.Lm = P.Lm;
+    p.R = P.Lm * P.L2;
     p.jmax = P.jmax;
     p.shift = P.shift;
     p.off = P.off;
@@ -207,6 +228,7 @@ void fill_params(const Plan& P, const uint64_t* u, const uint64_t* v, uint64_t* 
     p.tw = tw.tw;
     p.tw1 = tw.sub1;
     p.tw2 = tw.sub2;
+    p.twm = tw.subm;
 }
 
 tm_status plan_for(tm_kind kind, uint64_t n, Plan& P, int bt = 0, int bf = 0)
@@ -227,7 +249,12 @@ tm_status plan_for(tm_kind kind, uint64_t n, Plan& P, int bt = 0, int bf = 0)
         const char* e = getenv("TM_FORCE_B_FULL");
         if (e && *e) bf = atoi(e);
     }
-    if (!make_plan((int)kind, n, bt, bf, P)) {
+    uint32_t flm = 0;
+    {
+        const char* e = getenv("TM_FORCE_LM");
+        if (e && *e) flm = (uint32_t)atoi(e);
+    }
+    if (!make_plan((int)kind, n, bt, bf, P, flm)) {
         g_last_error = "unsupported size";
         return TM_ERR_UNSUPPORTED;
     }
@@ -253,7 +280,7 @@ tm_status run(const Plan& P, uint64_t* w, const uint64_t* u, const uint64_t* v, 
         return TM_ERR_INVALID;
     }
     TwEntry tw;
-    tm_status st = get_twiddles(P.M, P.L1, P.L2, s, tw);
+    tm_status st = get_twiddles(P.M, P.L1, P.Lm, P.L2, s, tw);
     if (st != TM_OK) return st;
     KParams p;
     uint64_t dummy_out = 0;
@@ -267,22 +294,34 @@ tm_status run(const Plan& P, uint64_t* w, const uint64_t* u, const uint64_t* v, 
         p.dbg_c = dc;
         p.dbg_x = dx;
     }
-    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    int ne = 0;
+    if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
     if (!launch_k1_any(P.kind, p, s)) {
         g_last_error = "no kernel for L1";
         return TM_ERR_UNSUPPORTED;
     }
-    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+    if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
+    if (P.Lm > 1) {
+        if (!launch_mid<false>(p, s)) {
+            g_last_error = "no kernel for Lm";
+            return TM_ERR_UNSUPPORTED;
+        }
+        if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
+    }
     if (!launch_k2(P.L2, p, s)) {
         g_last_error = "no kernel for L2";
         return TM_ERR_UNSUPPORTED;
     }
-    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+    if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
+    if (P.Lm > 1) {
+        launch_mid<true>(p, s);
+        if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
+    }
     launch_k3(P.L1, p, s);
-    if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+    if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
     if (mode == DIAG_RUN) launch_k4<true>(P.kind, p, s);
     else launch_k4<false>(P.kind, p, s);
-    if (ev) HIP_TRY(hipEventRecord(ev[4], s));
+    if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
     HIP_TRY(hipGetLastError());
     return TM_OK;
 }
@@ -329,6 +368,8 @@ tm_status tm_plan_query(tm_kind kind, uint64_t n_bits, tm_plan_info* out)
     out->L1 = P.L1;
     out->L2 = P.L2;
     out->workspace_bytes = P.ws_bytes;
+    out->Lm = P.Lm;
+    out->reserved = 0;
     return TM_OK;
 }
 
@@ -449,29 +490,33 @@ tm_status tm_profile_stages(tm_kind kind, uint64_t* w, const uint64_t* u, const 
                             hipStream_t stream, float* stage_ms, const char** names, int cap,
                             int* n_stages)
 {
-    static const char* kNames[4] = {"split_map_colfft", "rowfft_pointwise_rowifft",
-                                    "col_ifft", "backmap_round_carry"};
-    if (!stage_ms || !n_stages || cap < 4) {
+    static const char* kNames2[4] = {"split_map_colfft", "rowfft_pointwise_rowifft", "col_ifft",
+                                     "backmap_round_carry"};
+    static const char* kNames3[6] = {"split_map_colfft", "mid_colfft", "rowfft_pointwise_rowifft",
+                                     "mid_colifft", "col_ifft", "backmap_round_carry"};
+    if (!stage_ms || !n_stages || cap < 6) {
         g_last_error = "stage buffer too small";
         return TM_ERR_INVALID;
     }
     Plan P;
     tm_status st = plan_for(kind, n_bits, P);
     if (st != TM_OK) return st;
-    hipEvent_t ev[5];
-    for (int i = 0; i < 5; i++) HIP_TRY(hipEventCreate(&ev[i]));
+    const int ns = P.Lm > 1 ? 6 : 4;
+    const char** nm = P.Lm > 1 ? kNames3 : kNames2;
+    hipEvent_t ev[7];
+    for (int i = 0; i <= ns; i++) HIP_TRY(hipEventCreate(&ev[i]));
     st = run(P, w, u, v, workspace, workspace_bytes, stream, nullptr, RUN, nullptr, nullptr, ev);
     if (st == TM_OK) {
-        hipError_t e = hipEventSynchronize(ev[4]);
+        hipError_t e = hipEventSynchronize(ev[ns]);
         if (e != hipSuccess) st = hip_fail(e, "hipEventSynchronize");
-        for (int i = 0; st == TM_OK && i < 4; i++) {
+        for (int i = 0; st == TM_OK && i < ns; i++) {
             e = hipEventElapsedTime(&stage_ms[i], ev[i], ev[i + 1]);
             if (e != hipSuccess) st = hip_fail(e, "hipEventElapsedTime");
-            if (names) names[i] = kNames[i];
+            if (names) names[i] = nm[i];
         }
-        *n_stages = 4;
+        *n_stages = ns;
     }
-    for (int i = 0; i < 5; i++) (void)hipEventDestroy(ev[i]);
+    for (int i = 0; i <= ns; i++) (void)hipEventDestroy(ev[i]);
     return st;
 }
 

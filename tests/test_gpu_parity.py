@@ -215,3 +215,51 @@ def test_batched_matches_single():
     torch.cuda.synchronize()
     for r, w in zip(reqs, want):
         assert np.array_equal(to_host(r[4]), w)
+
+
+@pytest.mark.parametrize("lm", [2, 4])
+@pytest.mark.parametrize("n", [1 << 16, 100003])
+def test_forced_three_pass_split(monkeypatch, lm, n):
+    """The three-pass FFT split (middle pass of length Lm), forced at small n,
+    gives the oracle's products and the closed-form coefficients."""
+    monkeypatch.setenv("TM_FORCE_LM", str(lm))
+    tm = _tm()
+    assert tm.plan("lo", n)["Lm"] == lm
+    say("[parity] forced Lm=%d n=%d" % (lm, n))
+    u, v = inputs.operand_pair(n, 40 + lm)
+    check_all(u, v, n)
+
+
+def test_config_n2_26_parity():
+    """n = 2^26 (three-pass split chosen automatically): lo, hi, full vs the
+    oracle."""
+    n = 1 << 26
+    tm = _tm()
+    say("[parity] n=2^26 plans", {k: (tm.plan(k, n)["L1"], tm.plan(k, n)["Lm"], tm.plan(k, n)["L2"])
+                                  for k in ("lo", "hi", "full")})
+    u, v = inputs.operand_pair(n, 4)
+    glo, ghi, gfu = check_all(u, v, n, threads=16)
+    say("  guard lo %.4g hi %.4g full %.4g" % (glo.max_dist, ghi.max_dist, gfu.max_dist))
+
+
+def test_config_n2_30_residues_and_consistency():
+    """n = 2^30 (largest single instance): the full product checked modulo
+    three primes against the operands' residues (the oracle's residue
+    routine); the low product equals its low n bits and the high product is
+    one of the two allowed values derived from it."""
+    n = 1 << 30
+    L = n // 64
+    say("[parity] n=2^30")
+    u, v = inputs.operand_pair(n, 5)
+    full, gfu = run_kind("full", u, v, n)
+    for pmod in (2 ** 61 - 1, 2 ** 31 - 1, 1000000007):
+        assert oracle.residue(full, pmod) == oracle.residue(u, pmod) * oracle.residue(v, pmod) % pmod
+    lo, glo = run_kind("lo", u, v, n)
+    assert np.array_equal(lo, full[:L])
+    hi, ghi = run_kind("hi", u, v, n)
+    q = full[L:]
+    if not np.array_equal(hi, q):
+        assert np.any(full[:L] != 0) and oracle.to_int(hi) == oracle.to_int(q) + 1
+    for g in (glo, ghi, gfu):
+        assert g.flags == 0 and g.max_dist < 0.25, g.as_dict()
+    say("  guard lo %.4g hi %.4g full %.4g" % (glo.max_dist, ghi.max_dist, gfu.max_dist))

@@ -44,7 +44,7 @@ def lg(x):
     return (x - 1).bit_length()
 
 
-@pytest.mark.parametrize("n", [1 << 16, 1 << 24, 1 << 26, 12345, 2049, 1000003])
+@pytest.mark.parametrize("n", [1 << 16, 1 << 24, 1 << 26, 1 << 30, 12345, 2049, 1000003])
 def test_plans_satisfy_theorem_constraints(n):
     lo, hi, full = _plan("lo", n), _plan("hi", n), _plan("full", n)
     # low product: b >= 4, N >= 3, N b >= n (Theorem on the low product)
@@ -54,7 +54,8 @@ def test_plans_satisfy_theorem_constraints(n):
     # full product: N digits with N b >= n, length 2N
     assert full["digits"] * full["b"] >= n and full["N"] == 2 * full["digits"]
     for p in (lo, hi, full):
-        assert p["M"] * 2 == p["N"] and p["L1"] * p["L2"] == p["M"]
+        assert p["M"] * 2 == p["N"] and p["L1"] * p["Lm"] * p["L2"] == p["M"]
+        assert p["L1"] <= 1024 or p["Lm"] == 1
         odd = p["N"]
         while odd % 2 == 0:
             odd //= 2
@@ -90,3 +91,12 @@ def test_invalid_arguments_rejected_without_gpu():
     info = tm._PlanInfo()
     assert lib.tm_plan_query(1, 0, ctypes.byref(info)) == 1
     assert lib.tm_status_string(3) == b"rounding guard tripped"
+
+
+def test_three_pass_split_for_large_n():
+    """n = 2^30: M = L1 * Lm * L2 with a middle pass; n = 2^24 stays two-pass."""
+    lo, full = _plan("lo", 1 << 30), _plan("full", 1 << 30)
+    assert (lo["L1"], lo["Lm"], lo["L2"]) == (768, 64, 1024)
+    assert (full["L1"], full["Lm"], full["L2"]) == (1024, 64, 1024)
+    assert lo["N"] / full["N"] == 0.75
+    assert _plan("lo", 1 << 24)["Lm"] == 1 and _plan("full", 1 << 24)["Lm"] == 1
