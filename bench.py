@@ -33,12 +33,16 @@ def kernel_bytes(plan, n_bits, kind):
     operands (n/8 bytes each) and writes two packed spectra (2 M 16 = 16 N
     bytes); K2 reads them (16 N) and writes the product spectrum (8 N); K3
     reads and writes one complex array (8 N + 8 N); K4 reads the real
-    convolution (8 N) and writes the result limbs."""
+    convolution (8 N) and writes the result limbs.  With the three-pass
+    split the middle passes read and write both spectra (32 N) forward and
+    the product (16 N) inverse."""
     N = plan["N"]
     L = (n_bits + 63) // 64
     out = 16 * L if kind == "full" else 8 * L
     return {"split_map_colfft": 2 * 8 * L + 16 * N,
+            "mid_colfft": 32 * N,
             "rowfft_pointwise_rowifft": 24 * N,
+            "mid_colifft": 16 * N,
             "col_ifft": 16 * N,
             "backmap_round_carry": 8 * N + out}
 
