@@ -57,8 +57,11 @@ struct KParams {
     uint32_t nstatus;   // K4 workgroups
     uint32_t pad0;
     double invN, invM;
-    double cf[LMAX];    // (-eps)^r / r! or eps^r / r! for the forward map
-    double cb[LMAX];    // same for the back map
+    double cf[LMAX];        // c_r of the forward map: alpha (-eps)^r/r!, gamma eps^r/r!
+    double cb[LMAX];        // c_r of the back map: beta eps^r/r!, delta (-eps)^r/r!
+    double nf[LMAX][2];     // forward map in nested form: factor nf[r][0] y + nf[r][1]
+    double nb[LMAX][2];     // back map as a chain: factor nb[r][0] x + nb[r][1]
+    double bscale;          // 2^b / M (truncated products), 1 / M (full product)
     double2* za;        // operand u spectrum / convolution result
     double2* zb;        // operand v spectrum
     uint64_t* status;   // K4 look-back records, 2 words each
@@ -108,36 +111,32 @@ __device__ __forceinline__ int64_t bal_digit(const KParams& p, const uint64_t* x
     return d - (d >= h ? (1ll << b) : 0) + cin;
 }
 
-// Series coefficients (closed forms of the binomial definitions, Sections
-// 3.2 and 4.2); c = (-+eps)^r / r! supplied by the host.
-//   alpha_{k,r} = c (k/N) prod_{j=1}^{r-1} ((k+r)/N - j)
-//   gamma_{k,r} = c (k/N) prod_{j=1}^{r-1} ((k+r)/N + j)
-//   beta_{k,r}  = c prod_{j=0}^{r-1} (k/N + j)
-//   delta_{k,r} = c prod_{j=0}^{r-1} (k/N - j)
-__device__ __forceinline__ double coef_fwd(int kind, uint32_t k, int r, double invN, double c)
+// Series coefficients (Sections 3.2 and 4.2) with eps = 2^-b, x = k/N and
+// the (k + r) factor of the binomial definitions cancelled:
+//   alpha_{k,r} = c_r x prod_{j=1}^{r-1} ((k+r)/N - j),  c_r = (-eps)^r / r!
+//   gamma_{k,r} = c_r x prod_{j=1}^{r-1} ((k+r)/N + j),  c_r =   eps^r  / r!
+//   beta_{k,r}  = c_r prod_{j=0}^{r-1} (x + j),          c_r =   eps^r  / r!
+//   delta_{k,r} = c_r prod_{j=0}^{r-1} (x - j),          c_r = (-eps)^r / r!
+// These product forms serve the few indices next to the cyclic wrap; the
+// bulk of both maps uses the factored forms of row_map_fast / back_chain.
+template <int KIND>
+__device__ __forceinline__ double coef_fwd(const KParams& p, uint32_t k, int r)
 {
     if (r == 0) return 1.0;
-    const double x = (double)k * invN, y = (double)(k + (uint32_t)r) * invN;
-    double p = x;
-    if (kind == K_LO) {
-        for (int j = 1; j < r; j++) p *= (y - (double)j);
-    } else {
-        for (int j = 1; j < r; j++) p *= (y + (double)j);
-    }
-    return p * c;
+    const double x = (double)k * p.invN, y = (double)(k + (uint32_t)r) * p.invN;
+    double v = x * p.cf[r];
+    for (int j = 1; j < r; j++) v *= KIND == K_LO ? y - (double)j : y + (double)j;
+    return v;
 }
 
-__device__ __forceinline__ double coef_back(int kind, uint32_t k, int r, double invN, double c)
+template <int KIND>
+__device__ __forceinline__ double coef_back(const KParams& p, uint32_t k, int r)
 {
     if (r == 0) return 1.0;
-    const double x = (double)k * invN;
-    double p = 1.0;
-    if (kind == K_LO) {
-        for (int j = 0; j < r; j++) p *= (x + (double)j);
-    } else {
-        for (int j = 0; j < r; j++) p *= (x - (double)j);
-    }
-    return p * c;
+    const double x = (double)k * p.invN;
+    double v = p.cb[r];
+    for (int j = 0; j < r; j++) v *= KIND == K_LO ? x + (double)j : x - (double)j;
+    return v;
 }
 
 // Top digit F_N of the high-product split and theta = rho^-N F(rho) with
@@ -186,11 +185,18 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t ntiles)
 
 // Digits of one K1 tile row.  A row holds complex points m0 .. m0+W-1, i.e.
 // reals 2 m0 .. 2 m0 + 2W - 1; the truncated products' stencil also reads
-// the LMAX - 1 digits below.  The row's limbs are fetched once (independent
-// loads) and every digit is cut from registers.
-constexpr int k1_lo(int KIND) { return KIND == K_FULL ? 0 : LMAX - 1; }
-constexpr int k1_nd(int W, int KIND) { return 2 * W + k1_lo(KIND); }
-constexpr int k1_nlw(int ND) { return ((ND + 1) * 16 + 63) / 64 + 1; }
+// the LB - 1 digits below, LB being the largest series length an instance
+// serves (LB_FIXED for the instances with a compile-time digit size B,
+// LMAX for the generic ones).  The limbs under every row of a tile are
+// staged in LDS once; digits are cut from there.
+constexpr int LB_FIXED = 7;
+constexpr int k1_lb(int KIND, int B) { return KIND == K_FULL ? 1 : B ? LB_FIXED : LMAX; }
+constexpr int k1_lo(int KIND, int B) { return k1_lb(KIND, B) - 1; }
+constexpr int k1_nd(int W, int KIND, int B) { return 2 * W + k1_lo(KIND, B); }
+constexpr int k1_nlw(int ND, int B)
+{
+    return B ? ((ND + 1) * B + 64 + 63) / 64 : ((ND + 1) * 16 + 63) / 64 + 1;
+}
 
 template <int NLW>
 __device__ __forceinline__ uint64_t pick_limb(const uint64_t (&lim)[NLW], int i)
@@ -199,57 +205,6 @@ __device__ __forceinline__ uint64_t pick_limb(const uint64_t (&lim)[NLW], int i)
 #pragma unroll
     for (int k = 0; k < NLW; k++) r = (k == i) ? lim[k] : r;
     return r;
-}
-
-// d[t] = balanced digit at index kf + t: cyclic mod N for the truncated
-// products (their digits are all of the plain kind below N); for the full
-// product the top digit keeps its carry and indices >= digits are zero.
-template <int ND, int KIND>
-__device__ __forceinline__ void row_digits(const KParams& p, const uint64_t* x, int64_t kf,
-                                           int32_t (&d)[ND])
-{
-    constexpr int NLW = k1_nlw(ND);
-    const int b = p.b;
-    const int64_t top = KIND == K_FULL ? (int64_t)p.digits - 1 : (int64_t)p.N;
-    const bool fast = kf >= 0 && (KIND == K_FULL ? kf + ND <= top : true);
-    if (KIND == K_FULL && kf > top) {
-#pragma unroll
-        for (int t = 0; t < ND; t++) d[t] = 0;
-        return;
-    }
-    if (fast) {
-        const int64_t p0 = (kf - 1) * b - p.shift;  // bit of the first 2b-bit field
-        const int64_t l0 = p0 >= 0 ? p0 >> 6 : -((63 - p0) >> 6);
-        uint64_t lim[NLW];
-#pragma unroll
-        for (int i = 0; i < NLW; i++) {
-            const int64_t li = l0 + i;
-            uint64_t v = (li >= 0 && li < (int64_t)p.L) ? x[li] : 0;
-            if (li == (int64_t)p.L - 1 && (p.n & 63)) v &= (1ull << (p.n & 63)) - 1;
-            lim[i] = v;
-        }
-        const int64_t mask = (1ll << b) - 1, h = 1ll << (b - 1);
-#pragma unroll
-        for (int t = 0; t < ND; t++) {
-            const int rel = (int)((kf + t - 1) * b - p.shift - l0 * 64);
-            const int li = rel >> 6, sh = rel & 63;
-            const uint64_t lo = pick_limb(lim, li), hi = pick_limb(lim, li + 1);
-            const uint64_t w = sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
-            const int64_t dprev = (int64_t)(w & mask), dd = (int64_t)((w >> b) & mask);
-            d[t] = (int32_t)(dd - (dd >= h ? (1ll << b) : 0) + (dprev >= h ? 1 : 0));
-        }
-    } else {
-#pragma unroll
-        for (int t = 0; t < ND; t++) {
-            int64_t k = kf + t;
-            if (KIND == K_FULL) {
-                d[t] = k <= top ? (int32_t)bal_digit(p, x, k, p.digits, true) : 0;
-            } else {
-                if (k < 0) k += p.N;
-                d[t] = (int32_t)bal_digit(p, x, k, p.digits, false);
-            }
-        }
-    }
 }
 
 // Window start of a row: first field at bit p0 = (kf - 1) b - shift, limb
@@ -269,92 +224,183 @@ __device__ __forceinline__ uint64_t limb_at(const KParams& p, const uint64_t* x,
     return v;
 }
 
-// Digits of a row from its limb window staged in LDS (slimb = NLW limbs).
-template <int ND, int NLW, int KIND>
-__device__ __forceinline__ void row_digits_lds(const KParams& p, const uint64_t* x, int64_t kf,
-                                               const uint64_t* slimb, int32_t (&d)[ND])
+// Balanced digits from the b-bit fields f_i = d_(kf-1+i) of a window:
+// U = d - 2^b [d >= 2^(b-1)] + [d_prev >= 2^(b-1)], i.e. the field read as
+// a signed b-bit number plus the sign bit of the field below.
+
+// Compile-time digit size B: the window is aligned once (funnel shifts by
+// the row's bit offset), then every field sits at a fixed bit position.
+template <int ND, int B, int NLW>
+__device__ __forceinline__ void row_digits_fixed(const uint64_t* slimb, int rel0, int32_t (&d)[ND])
+{
+    constexpr int NF = ND + 1;
+    constexpr int NA = (NF * B + 31) / 32;
+    static_assert(NA + 2 <= 2 * NLW, "staged window too short");
+    uint32_t w[2 * NLW];
+#pragma unroll
+    for (int i = 0; i < NLW; i++) {
+        const uint64_t l = slimb[i];
+        w[2 * i] = (uint32_t)l;
+        w[2 * i + 1] = (uint32_t)(l >> 32);
+    }
+    const bool odd = rel0 >= 32;
+    const uint32_t sh = (uint32_t)rel0 & 31u;
+    uint32_t a[NA + 1];
+#pragma unroll
+    for (int k = 0; k <= NA; k++) a[k] = odd ? w[k + 1] : w[k];
+#pragma unroll
+    for (int k = 0; k < NA; k++) a[k] = __builtin_amdgcn_alignbit(a[k + 1], a[k], sh);
+    int32_t f[NF];
+#pragma unroll
+    for (int i = 0; i < NF; i++) {
+        const int pos = i * B, wi = pos >> 5, o = pos & 31;
+        const uint32_t v = o + B <= 32 ? a[wi] >> o : __builtin_amdgcn_alignbit(a[wi + 1], a[wi], o);
+        f[i] = (int32_t)(v << (32 - B)) >> (32 - B);
+    }
+#pragma unroll
+    for (int t = 0; t < ND; t++) d[t] = f[t + 1] + (int32_t)((uint32_t)f[t] >> 31);
+}
+
+// Runtime digit size, staged window.
+template <int ND>
+__device__ __forceinline__ void row_digits_var(const KParams& p, const uint64_t* slimb, int rel0,
+                                               int32_t (&d)[ND])
 {
     const int b = p.b;
-    const int64_t top = KIND == K_FULL ? (int64_t)p.digits - 1 : (int64_t)p.N;
-    if (KIND == K_FULL && kf > top) {
+    const int64_t mask = (1ll << b) - 1, h = 1ll << (b - 1);
 #pragma unroll
-        for (int t = 0; t < ND; t++) d[t] = 0;
-        return;
+    for (int t = 0; t < ND; t++) {
+        const int rel = rel0 + t * b;
+        const int li = rel >> 6, sh = rel & 63;
+        const uint64_t lo = slimb[li], hi = slimb[li + 1];
+        const uint64_t w = sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
+        const int64_t dprev = (int64_t)(w & mask), dd = (int64_t)((w >> b) & mask);
+        d[t] = (int32_t)(dd - (dd >= h ? (1ll << b) : 0) + (dprev >= h ? 1 : 0));
     }
-    const bool fast = kf >= 0 && (KIND == K_FULL ? kf + ND <= top : true);
-    if (fast) {
-        int64_t l0;
-        int rel0;
-        row_window(p, kf, l0, rel0);
-        const int64_t mask = (1ll << b) - 1, h = 1ll << (b - 1);
+}
+
+// Runtime digit size, limbs fetched into registers (tiles too small to
+// stage the limbs).
+template <int ND>
+__device__ __forceinline__ void row_digits_reg(const KParams& p, const uint64_t* x, int64_t kf,
+                                               int32_t (&d)[ND])
+{
+    constexpr int NLW = k1_nlw(ND, 0);
+    const int b = p.b;
+    int64_t l0;
+    int rel0;
+    row_window(p, kf, l0, rel0);
+    uint64_t lim[NLW];
 #pragma unroll
-        for (int t = 0; t < ND; t++) {
-            const int rel = rel0 + t * b;
-            const int li = rel >> 6, sh = rel & 63;
-            const uint64_t lo = slimb[li], hi = slimb[li + 1];
-            const uint64_t w = sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
-            const int64_t dprev = (int64_t)(w & mask), dd = (int64_t)((w >> b) & mask);
-            d[t] = (int32_t)(dd - (dd >= h ? (1ll << b) : 0) + (dprev >= h ? 1 : 0));
-        }
-    } else {
+    for (int i = 0; i < NLW; i++) lim[i] = limb_at(p, x, l0 + i);
+    const int64_t mask = (1ll << b) - 1, h = 1ll << (b - 1);
 #pragma unroll
-        for (int t = 0; t < ND; t++) {
-            int64_t k = kf + t;
-            if (KIND == K_FULL) {
-                d[t] = k <= top ? (int32_t)bal_digit(p, x, k, p.digits, true) : 0;
-            } else {
-                if (k < 0) k += p.N;
-                d[t] = (int32_t)bal_digit(p, x, k, p.digits, false);
-            }
+    for (int t = 0; t < ND; t++) {
+        const int rel = rel0 + t * b;
+        const int li = rel >> 6, sh = rel & 63;
+        const uint64_t lo = pick_limb(lim, li), hi = pick_limb(lim, li + 1);
+        const uint64_t w = sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
+        const int64_t dprev = (int64_t)(w & mask), dd = (int64_t)((w >> b) & mask);
+        d[t] = (int32_t)(dd - (dd >= h ? (1ll << b) : 0) + (dprev >= h ? 1 : 0));
+    }
+}
+
+// Digits of a row that touches index 0 or the top: cyclic mod N for the
+// truncated products (their digits are all of the plain kind below N); for
+// the full product the top digit keeps its carry and indices >= digits are
+// zero.
+template <int ND, int KIND>
+__device__ __forceinline__ void row_digits_edge(const KParams& p, const uint64_t* x, int64_t kf,
+                                                int32_t (&d)[ND])
+{
+    const int64_t top = (int64_t)p.digits - 1;
+#pragma unroll
+    for (int t = 0; t < ND; t++) {
+        int64_t k = kf + t;
+        if (KIND == K_FULL) {
+            d[t] = (k >= 0 && k <= top) ? (int32_t)bal_digit(p, x, k, p.digits, true) : 0;
+        } else {
+            if (k < 0) k += p.N;
+            d[t] = (int32_t)bal_digit(p, x, k, p.digits, false);
         }
     }
 }
 
-// G_(2m0+2c+e) for one row from its digits d (d[t] = digit 2 m0 - LO + t):
-//   full: the digits themselves;
-//   low:  G = alpha* U   (Prop. approximating alpha*), cyclic indices;
-//   high: G = gamma* F'  with F'_k = F_k + 2^(-kb) F_N  (F mod C by eq.
-//         reduction-modC with rho ~ 2^b, Prop. approximating gamma-dagger).
-template <int W, int KIND, int ND>
-__device__ __forceinline__ void row_map(const KParams& p, uint32_t m0, double FN,
-                                        const int32_t (&d)[ND], double2* g)
+// G_j, j = j0 .. j0 + 2W - 1 (j0 = kf + LB - 1), away from the wrap:
+//   low:  G = alpha* U  (Prop. approximating alpha*),
+//   high: G = gamma* F' (Prop. approximating gamma-dagger; F'_k = F_k for
+//         k >= jmax).
+// With y = j/N the coefficient alpha_{j-r,r} = c_r x_(j-r) pi_(r-1)(y),
+// pi_m(y) = prod_{i=1}^m (y - i) (gamma: y + i), so with V_k = x_k U_k
+//   G_j = U_j + c_1 (V_(j-1) + k_1 (y -+ 1) (V_(j-2) + k_2 (y -+ 2) (...)))
+// where k_r = c_(r+1) / c_r: two FMAs per series term.  The host zeroes
+// the factors from r = lam - 1 on, which cuts the nest at the plan's lam.
+template <int W, int ND, int LB>
+__device__ __forceinline__ void row_map_fast(const KParams& p, int64_t kf, const int32_t (&d)[ND],
+                                             double2* g)
 {
-    constexpr int LO = k1_lo(KIND);
-    if constexpr (KIND == K_FULL) {
+    constexpr int LO = LB - 1;
+    static_assert(ND == 2 * W + LO, "row digits");
+    double v[ND];
+    const double x0 = (double)kf * p.invN;
 #pragma unroll
-        for (int c = 0; c < W; c++) g[c] = make_double2((double)d[2 * c], (double)d[2 * c + 1]);
-    } else {
-        const uint32_t N = p.N;
+    for (int i = 0; i < ND; i++) v[i] = fma((double)i, p.invN, x0) * (double)d[i];
+    const double y0 = (double)(kf + LO) * p.invN;
+    double o[2 * W];
 #pragma unroll
-        for (int c = 0; c < W; c++) {
-            double s[2] = {0.0, 0.0};
+    for (int t = 0; t < 2 * W; t++) {
+        const double y = fma((double)t, p.invN, y0);
+        double s = v[t];
 #pragma unroll
-            for (int e = 0; e < 2; e++) {
-                const uint32_t j = 2 * m0 + 2 * c + e;
+        for (int r = LB - 2; r >= 1; r--) s = fma(fma(p.nf[r][0], y, p.nf[r][1]), s, v[t + LO - r]);
+        o[t] = fma(p.cf[1], s, (double)d[t + LO]);
+    }
 #pragma unroll
-                for (int r = 0; r < LMAX; r++) {
-                    if (r < p.lam) {
-                        const uint32_t k = j >= (uint32_t)r ? j - r : j + N - r;
-                        double f = (double)d[2 * c + e - r + LO];
-                        if (KIND == K_HI && k < p.jmax) f += ldexp(FN, -(int)k * p.b);
-                        s[e] = fma(coef_fwd(KIND, k, r, p.invN, p.cf[r]), f, s[e]);
-                    }
+    for (int c = 0; c < W; c++) g[c] = make_double2(o[2 * c], o[2 * c + 1]);
+}
+
+// The same maps term by term, for rows next to the wrap: cyclic indices,
+// and for the high product F'_k = F_k + 2^(-kb) F_N (F mod C by eq.
+// reduction-modC with rho ~ 2^b).
+template <int W, int KIND, int ND, int LB>
+__device__ __forceinline__ void row_map_edge(const KParams& p, uint32_t m0, double FN,
+                                             const int32_t (&d)[ND], double2* g)
+{
+    constexpr int LO = LB - 1;
+    const uint32_t N = p.N;
+#pragma unroll
+    for (int c = 0; c < W; c++) {
+        double s[2] = {0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < 2; e++) {
+            const uint32_t j = 2 * m0 + 2 * c + e;
+#pragma unroll
+            for (int r = 0; r < LB; r++) {
+                if (r < p.lam) {
+                    const uint32_t k = j >= (uint32_t)r ? j - r : j + N - r;
+                    double f = (double)d[2 * c + e - r + LO];
+                    if (KIND == K_HI && k < p.jmax) f += ldexp(FN, -(int)k * p.b);
+                    s[e] = fma(coef_fwd<KIND>(p, k, r), f, s[e]);
                 }
             }
-            g[c] = make_double2(s[0], s[1]);
         }
+        g[c] = make_double2(s[0], s[1]);
     }
 }
 
-template <int L1, int W, int KIND>
+// K1: split + map + column FFT for one column tile of the L1 x R matrix
+// (M = L1 R, R = Lm L2; element (k1, col) is point m = k1 R + col).
+// B: compile-time digit size (0: runtime p.b).
+template <int L1, int W, int KIND, int B>
 __global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
 {
     static_assert(L1 * W <= TILE, "tile too large");
     constexpr int PER = (L1 * W + NT - 1) / NT;
-    constexpr int ND = k1_nd(W, KIND), LO = k1_lo(KIND), NLW = k1_nlw(ND);
+    constexpr int LB = k1_lb(KIND, B), LO = LB - 1, ND = k1_nd(W, KIND, B), NLW = k1_nlw(ND, B);
     constexpr int TE = padded(L1 * W);
     // limb windows staged in the tile area when they fit
     constexpr bool STAGE = L1 * NLW * 8 <= TE * 16;
+    static_assert(STAGE || B == 0, "compile-time digit sizes need staged limbs");
     constexpr int RPT = (L1 + NT - 1) / NT;
     __shared__ double2 tile[TE];
     __shared__ double2 twl[twl_size(L1)];
@@ -403,19 +449,49 @@ __global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
     }
     __syncthreads();
     const double FN = KIND == K_HI ? s_FN : 0.0;
+    // rows away from index 0 (and, for the full product, from the top digit)
+    // take the fast path; the others the term-by-term one
+    const int64_t kf_min = KIND == K_HI ? (int64_t)p.jmax : 0;
+    const int64_t top = (int64_t)p.digits - 1;
     double2 g[RPT][W];
 #pragma unroll
     for (int rr = 0; rr < RPT; rr++) {
         const int j1 = tid + rr * NT;
         if (L1 % NT == 0 || j1 < L1) {
             const uint32_t m0 = (uint32_t)j1 * L2 + c0;
+            const int64_t kf = 2 * (int64_t)m0 - LO;
+            const bool fast = kf >= kf_min && (KIND != K_FULL || kf + ND <= top);
             int32_t d[ND];
-            if constexpr (STAGE)
-                row_digits_lds<ND, NLW, KIND>(p, x, 2 * (int64_t)m0 - LO,
-                                              reinterpret_cast<const uint64_t*>(tile) + j1 * NLW, d);
-            else
-                row_digits<ND, KIND>(p, x, 2 * (int64_t)m0 - LO, d);
-            row_map<W, KIND, ND>(p, m0, FN, d, g[rr]);
+            if (fast) {
+                if constexpr (STAGE) {
+                    int64_t l0;
+                    int rel0;
+                    row_window(p, kf, l0, rel0);
+                    const uint64_t* sl = reinterpret_cast<const uint64_t*>(tile) + j1 * NLW;
+                    if constexpr (B > 0)
+                        row_digits_fixed<ND, B, NLW>(sl, rel0, d);
+                    else
+                        row_digits_var<ND>(p, sl, rel0, d);
+                } else {
+                    row_digits_reg<ND>(p, x, kf, d);
+                }
+                if constexpr (KIND == K_FULL) {
+#pragma unroll
+                    for (int c = 0; c < W; c++)
+                        g[rr][c] = make_double2((double)d[2 * c], (double)d[2 * c + 1]);
+                } else {
+                    row_map_fast<W, ND, LB>(p, kf, d, g[rr]);
+                }
+            } else {
+                row_digits_edge<ND, KIND>(p, x, kf, d);
+                if constexpr (KIND == K_FULL) {
+#pragma unroll
+                    for (int c = 0; c < W; c++)
+                        g[rr][c] = make_double2((double)d[2 * c], (double)d[2 * c + 1]);
+                } else {
+                    row_map_edge<W, KIND, ND, LB>(p, m0, FN, d, g[rr]);
+                }
+            }
         }
     }
     if constexpr (STAGE) __syncthreads();
@@ -737,63 +813,76 @@ __device__ __forceinline__ double wave_max(double v)
 //         H_i = sum_r delta_{i-r,r} W_(i-r) (r <= i) + sum_j 2^(-jb)
 //         sum_{r > i-j} delta_{N+i-j-r,r} W_(N+i-j-r)  (X^(N+s) = sum_j
 //         2^(-jb) X^(s+j) mod C)
-// The sums use the unnormalised q = M W.
-__device__ __forceinline__ double back_lo(const KParams& p, const double* sq, uint64_t base, uint32_t i)
+// The sums use the unnormalised q = M W.  back_edge_* evaluate them term by
+// term for the indices next to the wrap (i < K4_HALO) and the top index
+// i = N of the high product; all other indices use back_chain.
+template <int KIND>
+__device__ double back_edge_sum(const KParams& p, const double* sq, uint32_t i)
 {
-    const uint32_t N = p.N;
-    const int o = (int)((int64_t)i - (int64_t)base) + K4_HALO;
-    double s = 0.0;
-#pragma unroll
-    for (int r = 0; r < LMAX; r++) {
-        if (r < p.lam) {
-            const uint32_t k = i >= (uint32_t)r ? i - r : i + N - r;
-            s = fma(coef_back(K_LO, k, r, p.invN, p.cb[r]), sq[o - r], s);
-        }
-    }
-    if (i >= 1 && i < (uint32_t)p.lam) {
-        double t = 0.0;
-        for (int r = (int)i; r < p.lam; r++)
-            t = fma(coef_back(K_LO, N + i - 1 - r, r, p.invN, p.cb[r]), sq[o - 1 - r], t);
-        s = fma(-ldexp(1.0, -p.b), t, s);
-    }
-    return s;
-}
-
-// Wrapped part of H_i (i < lam + jmax, workgroup 0 only):
-// sum_j 2^(-jb) sum_{r > i-j} delta_{N+i-j-r,r} W_(N+i-j-r).
-__device__ double back_hi_wrap(const KParams& p, const double* sq, uint32_t i)
-{
-    const uint32_t N = p.N;
+    // unwrapped part: sum_{r <= i} coef_{i-r,r} q_(i-r)   (workgroup 0: o = i)
     const int o = (int)i + K4_HALO;
     double s = 0.0;
-    for (int j = 0; j <= (int)i && j <= (int)p.jmax; j++) {
-        double t = 0.0;
-        for (int r = (int)i - j + 1; r < p.lam; r++)
-            t = fma(coef_back(K_HI, N + i - j - r, r, p.invN, p.cb[r]), sq[o - j - r], t);
-        s = fma(ldexp(1.0, -j * p.b), t, s);
+    for (int r = 0; r < p.lam && r <= (int)i; r++) s = fma(coef_back<KIND>(p, i - r, r), sq[o - r], s);
+    if (KIND == K_LO) {
+        for (int r = (int)i + 1; r < p.lam; r++) s = fma(coef_back<KIND>(p, p.N + i - r, r), sq[o - r], s);
+        if (i >= 1 && i < (uint32_t)p.lam) {
+            double t = 0.0;
+            for (int r = (int)i; r < p.lam; r++)
+                t = fma(coef_back<KIND>(p, p.N + i - 1 - r, r), sq[o - 1 - r], t);
+            s = fma(-ldexp(1.0, -p.b), t, s);
+        }
+    } else {
+        for (int j = 0; j <= (int)i && j <= (int)p.jmax; j++) {
+            double t = 0.0;
+            for (int r = (int)i - j + 1; r < p.lam; r++)
+                t = fma(coef_back<KIND>(p, p.N + i - j - r, r), sq[o - j - r], t);
+            s = fma(ldexp(1.0, -j * p.b), t, s);
+        }
     }
     return s;
 }
 
-// H_i: the unwrapped terms, plus the precomputed wrapped part swrap[i]
-// for i < K4_HALO in workgroup 0.
-__device__ __forceinline__ double back_hi(const KParams& p, const double* sq, const double* swrap,
-                                          uint64_t base, uint32_t i)
+// x_i for i < K4_HALO (workgroup 0) from se[i + 1] = the sum of
+// back_edge_sum at index i (se[0] = 0: the index below 0).
+template <int KIND>
+__device__ __forceinline__ double back_edge(const KParams& p, const double* se, uint32_t i, double thW)
 {
-    const int o = (int)((int64_t)i - (int64_t)base) + K4_HALO;
-    double s = 0.0;
-#pragma unroll
-    for (int r = 0; r < LMAX; r++) {
-        if (r < p.lam && (uint32_t)r <= i) s = fma(coef_back(K_HI, i - r, r, p.invN, p.cb[r]), sq[o - r], s);
-    }
-    if (i < (uint32_t)K4_HALO) s += swrap[i];
-    return s;
+    if (KIND == K_LO) return ldexp(se[i + 1] * p.invM, p.b);
+    return ldexp(fma(-ldexp(1.0, -p.b), se[i], se[i + 1]) * p.invM - ldexp(thW, -(int)i * p.b), p.b);
 }
 
-template <int KIND, bool DIAG>
+// The back maps away from the wrap, as a chain per input: with x = k/N,
+// beta_{k,r} = c_r prod_{j<r} (x + j) (delta: x - j), so the contributions
+// tau_r = 2^b/M beta_{k,r} q_k of input k to outputs k + r follow from
+// tau_(r+1) = tau_r (c_(r+1)/c_r) (x +- r): two FMAs per term.  The host
+// zeroes the factor at r = lam - 1, ending every chain at the plan's lam.
+// acc[o] = 2^b/M (beta* q)_(i0 - OFF + o), o < NOUT.
+template <int LB, int NOUT, int OFF>
+__device__ __forceinline__ void back_chain(const KParams& p, const double* sq, int s0, int64_t k0,
+                                           double (&acc)[NOUT])
+{
+    constexpr int NIN = NOUT + LB - 1;
+#pragma unroll
+    for (int o = 0; o < NOUT; o++) acc[o] = 0.0;
+    const double x0 = (double)k0 * p.invN;
+#pragma unroll
+    for (int e = 0; e < NIN; e++) {
+        double tau = sq[s0 + e] * p.bscale;
+        const double xk = fma((double)e, p.invN, x0);
+#pragma unroll
+        for (int r = 0; r < LB; r++) {
+            const int o = e + r - (LB - 1);
+            if (o >= 0 && o < NOUT) acc[o] += tau;
+            if (r + 1 < LB && o + 1 < NOUT) tau *= fma(p.nb[r][0], xk, p.nb[r][1]);
+        }
+    }
+}
+
+template <int KIND, bool DIAG, int B>
 __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
 {
     constexpr int NW = NT4 / 64;
+    constexpr int LB = KIND == K_FULL ? 1 : B ? LB_FIXED : LMAX;
     __shared__ uint32_t s_g;
     __shared__ int64_t s_cin;
     __shared__ double s_thW;
@@ -801,7 +890,7 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
     __shared__ int64_t sWA[NW], sWT[NW];
     __shared__ double sGD[NW], sGA[NW];
     __shared__ uint32_t sGF;
-    __shared__ double swrap[K4_HALO];
+    __shared__ double s_edge[K4_HALO + 1];
     uint16_t* sd = reinterpret_cast<uint16_t*>(sq);  // digits reuse the q staging area
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const double* q = reinterpret_cast<const double*>(p.za);
@@ -815,7 +904,7 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
     const double thW = KIND == K_HI ? s_thW : 0.0;
     const uint64_t base = (uint64_t)g * DPW;
     const uint64_t i0 = base + (uint64_t)tid * DPT;
-    const int b = p.b;
+    const int b = B ? B : p.b;
 
     // stage q[base - HALO, base + DPW) (zero outside [0, N))
     if (tid == 0) sGF = 0;
@@ -826,61 +915,63 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
     }
     __syncthreads();
 
-    // x_i (see back_lo / back_hi) and rounded coefficients, with the guard
+    // x_i (see back_edge / back_chain) and rounded coefficients, with the guard
     double xv[DPT];
     if constexpr (KIND == K_FULL) {
 #pragma unroll
-        for (int t = 0; t < DPT; t++) xv[t] = sq[tid * DPT + t + K4_HALO] * p.invM;
-    } else if constexpr (KIND == K_LO) {
-#pragma unroll
-        for (int t = 0; t < DPT; t++) {
-            const uint64_t i = i0 + t;
-            xv[t] = i < p.ncoef ? ldexp(back_lo(p, sq, base, (uint32_t)i) * p.invM, b) : 0.0;
-        }
+        for (int t = 0; t < DPT; t++) xv[t] = sq[tid * DPT + t + K4_HALO] * p.bscale;
     } else {
-        // wrapped terms of H (workgroup 0), one thread per index
-        if (base == 0) {
-            if (tid < K4_HALO)
-                swrap[tid] = (uint32_t)tid < (uint32_t)p.lam + p.jmax ? back_hi_wrap(p, sq, tid) : 0.0;
-            __syncthreads();
-        }
-        // H for i0-1 .. i0+DPT-1, then J_i = (H_i - 2^-b H_(i-1)) / M - theta_W 2^(-ib)
-        const double eps = ldexp(1.0, -b);
-        double hprev = (i0 >= 1 && i0 - 1 < p.N) ? back_hi(p, sq, swrap, base, (uint32_t)(i0 - 1)) : 0.0;
+        constexpr int OFF = KIND == K_HI ? 1 : 0;
+        constexpr int NOUT = DPT + OFF;
+        double acc[NOUT];
+        const int s0 = tid * DPT + K4_HALO - OFF - (LB - 1);
+        back_chain<LB, NOUT, OFF>(p, sq, s0, (int64_t)i0 - OFF - (LB - 1), acc);
+        if constexpr (KIND == K_LO) {
 #pragma unroll
-        for (int t = 0; t < DPT; t++) {
-            const uint64_t i = i0 + t;
-            if (i >= p.ncoef) { xv[t] = 0.0; continue; }
-            if (i < p.N) {
-                const double h = back_hi(p, sq, swrap, base, (uint32_t)i);
-                xv[t] = ldexp(fma(-eps, hprev, h) * p.invM - ldexp(thW, -(int)i * b), b);
-                hprev = h;
-            } else {
-                xv[t] = ldexp(-eps * hprev * p.invM + thW, b);
+            for (int t = 0; t < DPT; t++) xv[t] = acc[t];
+        } else {
+            const double eps = ldexp(1.0, -b);
+#pragma unroll
+            for (int t = 0; t < DPT; t++) xv[t] = fma(-eps, acc[t], acc[t + 1]);
+            // top coefficient: 2^b J_N = -2^-b 2^b H_(N-1) + 2^b theta_W
+            if (base + DPW > p.N) {
+#pragma unroll
+                for (int t = 0; t < DPT; t++)
+                    if (i0 + t == p.N) xv[t] = fma(-eps, acc[t], ldexp(thW, b));
             }
+        }
+        if (base == 0) {
+            // indices next to the wrap, one sum per thread
+            if (tid <= K4_HALO) s_edge[tid] = tid ? back_edge_sum<KIND>(p, sq, (uint32_t)tid - 1) : 0.0;
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < DPT; t++)
+                if (i0 + t < (uint64_t)K4_HALO) xv[t] = back_edge<KIND>(p, s_edge, (uint32_t)(i0 + t), thW);
         }
     }
 
+    // rint by the 1.5 2^52 shift (exact and ties-to-even for |x| < 2^51;
+    // larger |x| trip the guard's 2^50 bound)
+    constexpr double RMAG = 6755399441055744.0;
     int64_t c[DPT];
     double dmax = 0.0, amax = 0.0;
     uint32_t gflags = 0;
 #pragma unroll
     for (int t = 0; t < DPT; t++) {
         const uint64_t i = i0 + t;
-        c[t] = 0;
-        if (i < p.ncoef) {
-            const double r = rint(xv[t]);
-            const double ax = fabs(xv[t]);
-            dmax = fmax(dmax, fabs(xv[t] - r));
-            amax = fmax(amax, ax);
-            if (ax < 4503599627370496.0) c[t] = (int64_t)r;  // |x| < 2^52
-            if (DIAG) {
-                p.dbg_c[i] = c[t];
-                if (p.dbg_x) p.dbg_x[i] = xv[t];
-            }
-            if (KIND != K_FULL && i == 0 && (c[t] & ((1ll << b) - 1)) != 0) gflags |= TM_GUARD_C0;
+        const bool live = i < p.ncoef;
+        const double xs = live ? xv[t] : 0.0;
+        const double sh = xs + RMAG;
+        const double r = sh - RMAG;
+        c[t] = (int64_t)__double_as_longlong(sh) - (int64_t)__double_as_longlong(RMAG);
+        dmax = fmax(dmax, fabs(xs - r));
+        amax = fmax(amax, fabs(xs));
+        if (DIAG && live) {
+            p.dbg_c[i] = c[t];
+            if (p.dbg_x) p.dbg_x[i] = xs;
         }
     }
+    if (KIND != K_FULL && i0 == 0 && (c[0] & ((1ll << b) - 1)) != 0) gflags |= TM_GUARD_C0;
     // guard: reduce over the workgroup, then one atomic per field and only
     // when it raises the stored maximum (non-negative doubles order like
     // their bit patterns)
@@ -926,13 +1017,13 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
         l |= (unsigned __int128)(uint64_t)(sv & mask) << (t * b);
         carry = sv >> b;
     }
-    const int B = DPT * b;
+    const int BT = DPT * b;
     CarryF f;
-    if (l < ((unsigned __int128)1 << (B - 1))) {
+    if (l < ((unsigned __int128)1 << (BT - 1))) {
         f.A = carry - 1;
         f.T = l > (unsigned __int128)INT64_MAX ? INT64_MIN : -(int64_t)(uint64_t)l;
     } else {
-        unsigned __int128 t = ((unsigned __int128)1 << B) - l;
+        unsigned __int128 t = ((unsigned __int128)1 << BT) - l;
         f.A = carry;
         f.T = t > (unsigned __int128)INT64_MAX ? INT64_MAX : (int64_t)(uint64_t)t;
     }

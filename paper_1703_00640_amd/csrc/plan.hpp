@@ -79,7 +79,8 @@ inline bool split_M3(uint64_t M, uint32_t force_lm, uint32_t& L1, uint32_t& Lm, 
 {
     if (force_lm > 1) {
         Lm = force_lm;
-        return (Lm & (Lm - 1)) == 0 && Lm <= LM_MAX && M % Lm == 0 && split_M(M / Lm, L1, L2);
+        return (Lm & (Lm - 1)) == 0 && Lm <= LM_MAX && M % Lm == 0 && split_M(M / Lm, L1, L2) &&
+               L1 <= 1024;
     }
     for (Lm = 1; Lm <= LM_MAX; Lm *= 2) {
         if (M % Lm != 0) return false;

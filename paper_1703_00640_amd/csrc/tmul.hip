@@ -91,7 +91,7 @@ tm_status get_twiddles(uint64_t M, uint32_t L1, uint32_t Lm, uint32_t L2, hipStr
 
 constexpr int w_for(int L1)
 {
-    int lim = TILE / L1 < 16 ? TILE / L1 : 16;
+    int lim = TILE / L1 < 8 ? TILE / L1 : 8;
     int w = 1;
     while (w * 2 <= lim) w *= 2;
     return w;
@@ -99,18 +99,33 @@ constexpr int w_for(int L1)
 
 #define TM_L1_LIST(X) \
     X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) \
-    X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048) X(3072) X(4096)
+    X(256) X(384) X(512) X(768) X(1024)
 
-template <int KIND>
-bool launch_k1(uint32_t L1, const KParams& p, hipStream_t s)
+// Compile-time digit size of the K1 / K4 instances for a plan: the default
+// sizes (b = 11 truncated with lam <= LB_FIXED, b = 16 full) have their own
+// instances; every other plan runs the generic ones (B = 0).
+int fixed_b(int kind, const KParams& p)
+{
+    if (kind == TM_FULL) return p.b == B_FULL ? B_FULL : 0;
+    return p.b == B_TRUNC && p.lam <= LB_FIXED ? B_TRUNC : 0;
+}
+
+template <int KIND, int B>
+bool launch_k1_b(uint32_t L1, const KParams& p, hipStream_t s)
 {
     switch (L1) {
 #define X(V) \
-    case V: hipLaunchKernelGGL((k1_split_map_col<V, w_for(V), KIND>), dim3(p.R / w_for(V), 2), dim3(NT), 0, s, p); return true;
+    case V: hipLaunchKernelGGL((k1_split_map_col<V, w_for(V), KIND, B>), dim3(p.R / w_for(V), 2), dim3(NT), 0, s, p); return true;
         TM_L1_LIST(X)
 #undef X
     }
     return false;
+}
+
+template <int KIND, int BF>
+bool launch_k1(uint32_t L1, const KParams& p, hipStream_t s)
+{
+    return fixed_b(KIND, p) ? launch_k1_b<KIND, BF>(L1, p, s) : launch_k1_b<KIND, 0>(L1, p, s);
 }
 
 bool launch_k3(uint32_t L1, const KParams& p, hipStream_t s)
@@ -155,29 +170,64 @@ bool launch_mid(const KParams& p, hipStream_t s)
     return false;
 }
 
+template <bool DIAG, int KIND, int BF>
+void launch_k4_k(const KParams& p, hipStream_t s)
+{
+    dim3 g(p.nstatus);
+    if (fixed_b(KIND, p)) hipLaunchKernelGGL((k4_backmap_carry<KIND, DIAG, BF>), g, dim3(NT4), 0, s, p);
+    else hipLaunchKernelGGL((k4_backmap_carry<KIND, DIAG, 0>), g, dim3(NT4), 0, s, p);
+}
+
 template <bool DIAG>
 void launch_k4(int kind, const KParams& p, hipStream_t s)
 {
-    dim3 g(p.nstatus);
-    if (kind == TM_FULL) hipLaunchKernelGGL((k4_backmap_carry<K_FULL, DIAG>), g, dim3(NT4), 0, s, p);
-    else if (kind == TM_LO) hipLaunchKernelGGL((k4_backmap_carry<K_LO, DIAG>), g, dim3(NT4), 0, s, p);
-    else hipLaunchKernelGGL((k4_backmap_carry<K_HI, DIAG>), g, dim3(NT4), 0, s, p);
+    if (kind == TM_FULL) launch_k4_k<DIAG, K_FULL, B_FULL>(p, s);
+    else if (kind == TM_LO) launch_k4_k<DIAG, K_LO, B_TRUNC>(p, s);
+    else launch_k4_k<DIAG, K_HI, B_TRUNC>(p, s);
 }
 
 bool launch_k1_any(int kind, const KParams& p, hipStream_t s)
 {
-    if (kind == TM_FULL) return launch_k1<K_FULL>(p.L1, p, s);
-    if (kind == TM_LO) return launch_k1<K_LO>(p.L1, p, s);
-    return launch_k1<K_HI>(p.L1, p, s);
+    if (kind == TM_FULL) return launch_k1<K_FULL, B_FULL>(p.L1, p, s);
+    if (kind == TM_LO) return launch_k1<K_LO, B_TRUNC>(p.L1, p, s);
+    return launch_k1<K_HI, B_TRUNC>(p.L1, p, s);
 }
 
 // ------------------------------------------------------------ params
 
-double inv_fact(int r)
+// Series constants.  c_r: alpha (-eps)^r/r!, gamma eps^r/r! (forward),
+// beta eps^r/r!, delta (-eps)^r/r! (back).  Forward nested form (see
+// row_map_fast): factor k_r (y -+ r), k_r = c_(r+1)/c_r, for 1 <= r <= lam-2.
+// Back chain (see back_chain): factor k_r (x +- r) for 0 <= r <= lam-2.
+// Factors from r = lam - 1 on are zero.
+void fill_series(const Plan& P, KParams& p)
 {
-    double f = 1.0;
-    for (int i = 2; i <= r; i++) f *= i;
-    return 1.0 / f;
+    const double eps = ldexp(1.0, -P.b);
+    const bool lo = P.kind == TM_LO;
+    double e = 1.0, fact = 1.0;
+    for (int r = 0; r < LMAX; r++) {
+        if (r > 0) {
+            e *= eps;
+            fact *= r;
+        }
+        const double sgn = (r & 1) ? -1.0 : 1.0;
+        p.cf[r] = (lo ? sgn : 1.0) * e / fact;
+        p.cb[r] = (lo ? 1.0 : sgn) * e / fact;
+    }
+    for (int r = 0; r < LMAX; r++) {
+        p.nf[r][0] = p.nf[r][1] = 0.0;
+        p.nb[r][0] = p.nb[r][1] = 0.0;
+        if (P.kind == TM_FULL || r + 1 >= P.lam || r + 1 >= LMAX) continue;
+        const double kf = p.cf[r + 1] / p.cf[r];  // (-+eps) / (r + 1)
+        const double kb = p.cb[r + 1] / p.cb[r];
+        if (r >= 1) {
+            p.nf[r][0] = kf;
+            p.nf[r][1] = kf * (lo ? -(double)r : (double)r);
+        }
+        p.nb[r][0] = kb;
+        p.nb[r][1] = kb * (lo ? (double)r : -(double)r);
+    }
+    p.bscale = P.kind == TM_FULL ? 1.0 / (double)P.M : ldexp(1.0 / (double)P.M, P.b);
 }
 
 void fill_params(const Plan& P, const uint64_t* u, const uint64_t* v, uint64_t* w, void* ws,
@@ -209,16 +259,7 @@ void fill_params(const Plan& P, const uint64_t* u, const uint64_t* v, uint64_t* 
     p.nstatus = P.nstatus;
     p.invN = 1.0 / (double)P.N;
     p.invM = 1.0 / (double)P.M;
-    const double eps = ldexp(1.0, -P.b);
-    for (int r = 0; r < LMAX; r++) {
-        double e = 1.0;
-        for (int i = 0; i < r; i++) e *= eps;
-        double s_alt = (r & 1) ? -1.0 : 1.0;   // (-eps)^r sign
-        // forward map: alpha (low) has (-eps)^r, gamma (high) eps^r
-        p.cf[r] = (P.kind == TM_LO ? s_alt : 1.0) * e * inv_fact(r);
-        // back map: beta (low) eps^r, delta (high) (-eps)^r
-        p.cb[r] = (P.kind == TM_LO ? 1.0 : s_alt) * e * inv_fact(r);
-    }
+    fill_series(P, p);
     p.za = reinterpret_cast<double2*>(base + P.o_za);
     p.zb = reinterpret_cast<double2*>(base + P.o_zb);
     p.status = reinterpret_cast<uint64_t*>(base + P.o_status);
