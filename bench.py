@@ -8,6 +8,9 @@ fixed seed), inputs resident in HBM.  Prints one JSON line with
 * per-kind time and Mbit/s, and the lo/full and hi/full time ratios;
 * roofline: algorithmic bytes / time of the dominant kernel, timed with HIP
   events on the launch stream, against the 8 TB/s HBM peak;
+* serving: p50 / p99 latency and throughput of a mixed stream of requests
+  (n from 2^12 to 2^22 bits, all three kinds) through the library's
+  continuous-batching server, saturated and under Poisson arrivals;
 * cpu_baseline: the CPU oracle (Karatsuba on 64-bit limbs) computing the
   same three products for one operand pair, timed on the host cores.
 """
@@ -101,6 +104,35 @@ def pmc_pass(n_bits):
     print("pmc pass done", flush=True)
 
 
+def serving_bench(count=4096, n_streams=4):
+    """Mixed-request serving through the continuous-batching server: count
+    requests, n log-uniform over [2^12, 2^22] bits (whole limbs), kind
+    uniform over lo / hi / full, uniform random operands in pinned host
+    memory (copies in and out are part of every request).  First all
+    requests at t = 0 (saturation throughput R), then Poisson arrivals at
+    0.5 R and 0.9 R; latency = completion seen on the host - arrival."""
+    from paper_1703_00640_amd import inputs, serving
+    mix = inputs.serving_mix(count, seed=6)
+    m = serving.Mix(mix, seed=7)
+    sat, _, _ = serving.run(m, np.zeros(count), n_streams=n_streams)
+    out = {"workload": "%d requests, n log-uniform over [2^12, 2^22] bits, kind uniform "
+                       "lo/hi/full, host operands (pinned), pool 1 GiB, %d streams"
+                       % (count, n_streams),
+           "saturated": sat}
+    for frac in (0.5, 0.9):
+        rate = frac * sat["throughput_rps"]
+        arr = inputs.poisson_arrivals(count, rate, seed=8)
+        st, _, _ = serving.run(m, arr, n_streams=n_streams)
+        st["offered_rps"] = rate
+        out["poisson_%.1f" % frac] = st
+    for v in out.values():
+        if isinstance(v, dict):
+            for k in list(v):
+                if isinstance(v[k], float):
+                    v[k] = round(v[k], 6)
+    return out
+
+
 def cpu_baseline(n_bits, threads):
     import oracle
     from paper_1703_00640_amd import inputs
@@ -122,6 +154,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the mixed-request serving runs")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="run the counter-collection workload instead of the benchmark")
     args = ap.parse_args()
@@ -238,6 +271,8 @@ def main():
         "source_hash": source_hash(),
         "wall_s_timed": round(wall, 3),
     }
+    if not args.no_serve:
+        result["serving"] = serving_bench()
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         result["cpu_baseline"] = cpu_baseline(n, threads)

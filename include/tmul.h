@@ -192,6 +192,63 @@ tm_status tm_profile_stages(tm_kind kind, uint64_t* w, const uint64_t* u, const 
                             hipStream_t stream, float* stage_ms, const char** names,
                             int cap, int* n_stages);
 
+/*
+ * Build the per-device caches a call of (kind, n_bits) uses (twiddle tables)
+ * now, on `stream`, and wait for them.  Optional: every call builds them on
+ * first use; servers call this before their clock starts.
+ */
+tm_status tm_prepare(tm_kind kind, uint64_t n_bits, hipStream_t stream);
+
+/*
+ * Serving: continuous batching on the current device.
+ *
+ * A server owns one device memory pool of pool_bytes (allocated at
+ * creation), n_streams HIP streams and max_inflight request slots (0: 8 per
+ * stream).  Requests carry HOST pointers
+ * (tm_request.u, .v: n_bits-bit operands, read until the request
+ * completes; .w: result buffer of the tm_mul layout); pinned host memory
+ * lets the copies overlap.  Requests wait in submission order and each is
+ * admitted once a slot is free and its footprint (tm_server_footprint:
+ * operands, result, guard, workspace) can be carved out of the pool; it
+ * then runs on the
+ * stream with the fewest requests in flight (copy in, tm_mul, copy out).
+ * A request that does not fit reserves the bytes it waits for: requests
+ * behind it pass it only within the remaining free bytes.
+ * tm_server_poll retires finished requests, frees their memory and admits
+ * waiting ones, so requests that arrive while others run join as memory
+ * frees up, and their work overlaps on the device.  Results equal tm_mul's
+ * for the same (kind, n_bits) (the plan depends on them only).  A server is
+ * used from one host thread at a time.  The throughput / latency workload
+ * of a whole arrival trace runs through tm_serve_trace.
+ */
+typedef struct tm_server tm_server;
+
+size_t tm_server_footprint(tm_kind kind, uint64_t n_bits);  /* 0 if unsupported */
+tm_status tm_server_create(size_t pool_bytes, int n_streams, int max_inflight, tm_server** out);
+/* Queue one request (copied; guard_host: host tm_guard written on
+ * completion, or NULL).  *id identifies it in tm_server_poll.
+ * TM_ERR_INVALID if its footprint exceeds the pool. */
+tm_status tm_server_submit(tm_server* s, const tm_request* req, tm_guard* guard_host, uint64_t* id);
+/* Retire finished requests and admit waiting ones; writes up to cap
+ * (id, status) pairs of finished requests and returns their number (-1 on
+ * a null server).  Non-blocking. */
+int tm_server_poll(tm_server* s, uint64_t* ids, tm_status* status, int cap);
+size_t tm_server_pending(const tm_server* s);  /* queued + running */
+tm_status tm_server_drain(tm_server* s);       /* block until none pending */
+void tm_server_destroy(tm_server* s);          /* waits for running requests */
+
+/*
+ * Replay an arrival trace through a fresh server: request i is submitted
+ * at arrival_s[i] seconds (non-decreasing) after the start; latency_s[i]
+ * receives its completion time minus its arrival time, seen on the host's
+ * steady clock (-1 if it failed).  guards_host: count tm_guard or NULL.
+ * *makespan_s: start to last completion.  Caches for every (kind, n_bits)
+ * of the trace are built before the clock starts.
+ */
+tm_status tm_serve_trace(const tm_request* reqs, const double* arrival_s, size_t count,
+                         size_t pool_bytes, int n_streams, int max_inflight, double* latency_s,
+                         tm_guard* guards_host, double* makespan_s);
+
 const char* tm_status_string(tm_status s);
 const char* tm_last_error(void);
 void tm_release_caches(void);

@@ -16,7 +16,8 @@ import torch
 
 __all__ = ["mul", "mul_lo", "mul_hi", "mul_full", "mul_batched", "mul_checked",
            "coefficients", "profile_stages", "plan", "workspace_bytes", "Guard",
-           "TmulError", "KINDS", "library_path"]
+           "TmulError", "KINDS", "library_path", "prepare", "Server", "serve_trace",
+           "server_footprint"]
 
 KINDS = {"full": 0, "lo": 1, "hi": 2}
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -84,6 +85,27 @@ def _load():
     for name in ("tm_plan_query", "tm_mul", "tm_mul_full", "tm_mul_lo", "tm_mul_hi",
                  "tm_mul_batched", "tm_mul_checked", "tm_coefficients", "tm_profile_stages"):
         getattr(lib, name).restype = I32
+    lib.tm_prepare.argtypes = [I32, U64, P]
+    lib.tm_prepare.restype = I32
+    lib.tm_server_footprint.argtypes = [I32, U64]
+    lib.tm_server_footprint.restype = SZ
+    lib.tm_server_create.argtypes = [SZ, I32, I32, ctypes.POINTER(P)]
+    lib.tm_server_create.restype = I32
+    lib.tm_server_submit.argtypes = [P, ctypes.POINTER(_Request), ctypes.POINTER(Guard),
+                                     ctypes.POINTER(U64)]
+    lib.tm_server_submit.restype = I32
+    lib.tm_server_poll.argtypes = [P, ctypes.POINTER(U64), ctypes.POINTER(I32), I32]
+    lib.tm_server_poll.restype = I32
+    lib.tm_server_pending.argtypes = [P]
+    lib.tm_server_pending.restype = SZ
+    lib.tm_server_drain.argtypes = [P]
+    lib.tm_server_drain.restype = I32
+    lib.tm_server_destroy.argtypes = [P]
+    lib.tm_server_destroy.restype = None
+    lib.tm_serve_trace.argtypes = [ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_double), SZ,
+                                   SZ, I32, I32, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(Guard), ctypes.POINTER(ctypes.c_double)]
+    lib.tm_serve_trace.restype = I32
     lib.tm_status_string.argtypes = [I32]
     lib.tm_status_string.restype = ctypes.c_char_p
     lib.tm_last_error.argtypes = []
@@ -278,3 +300,100 @@ def profile_stages(kind, u, v, n_bits, out, workspace, stream=None):
                                      _stream_ptr(stream, u.device), ms, names, cap,
                                      ctypes.byref(nst)), "tm_profile_stages")
     return [(names[i].decode(), float(ms[i])) for i in range(nst.value)]
+
+
+# ------------------------------------------------------------------ serving
+
+def prepare(kind, n_bits, stream=None):
+    """Build the per-device caches of (kind, n_bits) now (optional)."""
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(_load().tm_prepare(_kind(kind), int(n_bits), ctypes.c_void_p(st.cuda_stream)),
+           "prepare")
+
+
+def server_footprint(kind, n_bits):
+    """Device pool bytes one request of (kind, n_bits) occupies in a Server."""
+    nb = _load().tm_server_footprint(_kind(kind), int(n_bits))
+    if nb == 0:
+        raise TmulError("unsupported (kind, n_bits) = (%s, %d)" % (kind, n_bits))
+    return nb
+
+
+def _host_buf(t, L, name):
+    if t.device.type != "cpu" or t.dtype not in (torch.uint64, torch.int64) \
+            or not t.is_contiguous() or t.numel() < L:
+        raise TmulError("%s must be a contiguous CPU int64/uint64 tensor of >= %d limbs" % (name, L))
+    return t.data_ptr()
+
+
+class Server:
+    """Continuous-batching server (tm_server_* in tmul.h): requests with
+    host tensors are admitted by device memory and overlap on the device.
+    Keep every submitted tensor alive until its request is polled."""
+
+    def __init__(self, pool_bytes=1 << 30, n_streams=4, max_inflight=0):
+        lib = _load()
+        h = ctypes.c_void_p()
+        _check(lib.tm_server_create(int(pool_bytes), int(n_streams), int(max_inflight),
+                                    ctypes.byref(h)), "server create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, kind, u, v, n_bits, out):
+        k, L = _kind(kind), nlimbs(n_bits)
+        nout = 2 * L if k == 0 else L
+        req = _Request(k, 0, int(n_bits), _host_buf(u, L, "u"), _host_buf(v, L, "v"),
+                       _host_buf(out, nout, "out"))
+        g = Guard()
+        rid = ctypes.c_uint64()
+        _check(_load().tm_server_submit(self._h, ctypes.byref(req), ctypes.byref(g),
+                                        ctypes.byref(rid)), "submit")
+        self._keep[rid.value] = (u, v, out, g)
+        return rid.value
+
+    def poll(self, cap=256):
+        """[(id, status, Guard)] of requests finished since the last poll."""
+        ids = (ctypes.c_uint64 * cap)()
+        sts = (ctypes.c_int * cap)()
+        n = _load().tm_server_poll(self._h, ids, sts, cap)
+        if n < 0:
+            raise TmulError("poll on a closed server")
+        return [(ids[i], sts[i], self._keep.pop(ids[i])[3]) for i in range(n)]
+
+    def pending(self):
+        return _load().tm_server_pending(self._h)
+
+    def drain(self):
+        _check(_load().tm_server_drain(self._h), "drain")
+
+    def close(self):
+        if self._h:
+            _load().tm_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def serve_trace(requests, arrival_s, pool_bytes=1 << 30, n_streams=4, max_inflight=0):
+    """Replay an arrival trace (tm_serve_trace).  requests: list of
+    (kind, u, v, n_bits, out) with CPU tensors (pinned for overlap).
+    Returns (latency_s list, guards list, makespan_s)."""
+    lib = _load()
+    cnt = len(requests)
+    reqs = (_Request * cnt)()
+    for i, (kind, u, v, n_bits, out) in enumerate(requests):
+        k, L = _kind(kind), nlimbs(n_bits)
+        reqs[i] = _Request(k, 0, int(n_bits), _host_buf(u, L, "u"), _host_buf(v, L, "v"),
+                           _host_buf(out, 2 * L if k == 0 else L, "out"))
+    arr = (ctypes.c_double * cnt)(*[float(a) for a in arrival_s])
+    lat = (ctypes.c_double * cnt)()
+    guards = (Guard * cnt)()
+    mk = ctypes.c_double()
+    _check(lib.tm_serve_trace(reqs, arr, cnt, int(pool_bytes), int(n_streams), int(max_inflight),
+                              lat, guards, ctypes.byref(mk)), "serve_trace")
+    return list(lat), [guards[i] for i in range(cnt)], mk.value

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtmul.so")
-SOURCES = [os.path.join(HERE, "csrc", "tmul.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "tmul.hip"), os.path.join(HERE, "csrc", "serve.cpp")]
 DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("kernels.hpp", "fft_tile.hpp", "plan.hpp")] \
     + [os.path.join(ROOT, "include", "tmul.h")]
 

@@ -425,6 +425,15 @@ tm_status tm_mul(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v
                nullptr);
 }
 
+tm_status tm_prepare(tm_kind kind, uint64_t n_bits, hipStream_t stream)
+{
+    Plan P;
+    tm_status st = plan_for(kind, n_bits, P);
+    if (st != TM_OK) return st;
+    TwEntry tw;
+    return get_twiddles(P.M, P.L1, P.Lm, P.L2, stream, tw);
+}
+
 tm_status tm_mul_full(uint64_t* w, const uint64_t* u, const uint64_t* v, uint64_t n_bits,
                       void* workspace, size_t workspace_bytes, hipStream_t stream,
                       tm_guard* guard_dev)

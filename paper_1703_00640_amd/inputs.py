@@ -67,3 +67,38 @@ def digit_pattern(n_bits, b, value, shift=0):
         bits[pos:pos + m] = field[:m]
     packed = np.packbits(bits[:64 * L], bitorder="little")
     return mask_top(np.frombuffer(packed.tobytes(), dtype="<u8").astype(np.uint64), n_bits)
+
+
+def serving_mix(count, seed, log2_lo=12, log2_hi=22):
+    """Request sizes and kinds of the mixed serving workload: n log-uniform
+    over [2^log2_lo, 2^log2_hi] bits, rounded to whole 64-bit limbs; kind
+    uniform over lo / hi / full.  Returns a list of (kind, n_bits)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    e = g.uniform(log2_lo, log2_hi, size=count)
+    n = np.maximum(1, np.rint(np.exp2(e) / 64.0)).astype(np.int64) * 64
+    kinds = g.integers(0, 3, size=count)
+    names = ("lo", "hi", "full")
+    return [(names[k], int(x)) for k, x in zip(kinds, n)]
+
+
+def poisson_arrivals(count, rate, seed):
+    """Arrival times (seconds) of a Poisson process of the given rate:
+    cumulative exponential inter-arrival gaps, the first arrival at 0."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    gaps = g.exponential(1.0 / rate, size=count)
+    gaps[0] = 0.0
+    return np.cumsum(gaps)
+
+
+def operand_slices(mix, seed):
+    """Operands for a request mix without one array per request: one random
+    limb pool as long as the largest request, and per request the offsets of
+    its u and v windows in it (seeded).  Returns (pool, [(ou, ov)])."""
+    Lmax = max(nlimbs(n) for _, n in mix)
+    pool = random_limbs(64 * 2 * Lmax, seed)
+    g = np.random.Generator(np.random.PCG64(seed + 1))
+    offs = []
+    for _, n in mix:
+        L = nlimbs(n)
+        offs.append((int(g.integers(0, 2 * Lmax - L + 1)), int(g.integers(0, 2 * Lmax - L + 1))))
+    return pool, offs

@@ -100,3 +100,26 @@ def test_three_pass_split_for_large_n():
     assert (full["L1"], full["Lm"], full["L2"]) == (1024, 64, 1024)
     assert lo["N"] / full["N"] == 0.75
     assert _plan("lo", 1 << 24)["Lm"] == 1 and _plan("full", 1 << 24)["Lm"] == 1
+
+
+def test_server_host_checks():
+    """Footprints and argument checks of the serving entry points (no GPU
+    work: every call below returns before touching the device)."""
+    import paper_1703_00640_amd as tm
+    lib = tm._load()
+    for kind, n in (("lo", 1 << 22), ("hi", 4096), ("full", 1 << 20)):
+        fp = tm.server_footprint(kind, n)
+        L = (n + 63) // 64
+        assert fp >= tm.workspace_bytes(kind, n) + (4 if kind == "full" else 3) * 8 * L
+        assert fp % 256 == 0
+    h = ctypes.c_void_p()
+    assert lib.tm_server_create(0, 4, 0, ctypes.byref(h)) == 1
+    assert lib.tm_server_create(1 << 20, 0, 0, ctypes.byref(h)) == 1
+    assert lib.tm_server_create(1 << 20, 2, -1, ctypes.byref(h)) == 1
+    assert lib.tm_server_poll(None, None, None, 0) == -1
+    assert lib.tm_server_pending(None) == 0
+    # arrivals must be non-decreasing
+    reqs = (tm._Request * 2)()
+    arr = (ctypes.c_double * 2)(1.0, 0.5)
+    lat = (ctypes.c_double * 2)()
+    assert lib.tm_serve_trace(reqs, arr, 2, 1 << 20, 2, 0, lat, None, None) == 1
