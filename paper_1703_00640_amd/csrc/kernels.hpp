@@ -28,12 +28,23 @@ enum { K_FULL = 0, K_LO = 1, K_HI = 2 };
 
 constexpr int NT = 256;         // threads per workgroup, every kernel
 constexpr int LMAX = 9;         // largest supported series length lambda
-constexpr int DPT = 7;          // digits per thread in K4
-constexpr int NT4 = 1024;       // threads per K4 workgroup
-constexpr int DPW = DPT * NT4;  // digits per workgroup in K4
+constexpr int DPT = TM_DPT;     // coefficients per thread in K4
+#ifndef TM_NT4
+#define TM_NT4 512
+#endif
+#ifndef TM_NT3
+#define TM_NT3 256
+#endif
+#ifndef TM_DPT
+#define TM_DPT 8
+#endif
+constexpr int NT4 = TM_NT4;     // threads per K4 workgroup
+constexpr int NT3 = TM_NT3;     // threads per K3 workgroup
+constexpr int DPW = DPT * NT4;  // coefficients per workgroup in K4
 constexpr int TILE = 4096;      // complex elements per column tile (64 KiB)
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 constexpr int K4_HALO = 32;        // q values staged below a K4 workgroup's range
+constexpr int64_t K4_CMAX = 1ll << 57;  // bound on the carries between limbs
 
 struct KParams {
     const uint64_t* u;
@@ -699,43 +710,43 @@ __global__ __launch_bounds__(NT) void k_mid_col(KParams p)
 // ------------------------------------------------------------------- K3
 
 template <int L1, int W>
-__global__ __launch_bounds__(NT) void k3_col_inverse(KParams p)
+__global__ __launch_bounds__(NT3) void k3_col_inverse(KParams p)
 {
     __shared__ double2 tile[padded(L1 * W)];
     __shared__ double2 twl[twl_size(L1)];
     const uint32_t L2 = p.R;  // row length of the L1 x R matrix
     const uint32_t c0 = xcd_tile(blockIdx.x, gridDim.x) * W;
-    load_twl<L1, NT>(twl, p.tw1);
-    constexpr int PER = (L1 * W + NT - 1) / NT;
-    static_assert(NT % W == 0, "W must divide NT");
+    load_twl<L1, NT3>(twl, p.tw1);
+    constexpr int PER = (L1 * W + NT3 - 1) / NT3;
+    static_assert(NT3 % W == 0, "W must divide NT3");
     const int tid = threadIdx.x;
     const uint32_t colt = c0 + tid % W;
     const uint32_t eb = (uint32_t)((uint64_t)colt * (uint32_t)(tid / W) % p.M);
-    const uint32_t es = (uint32_t)((uint64_t)colt * (uint32_t)(NT / W) % p.M);
+    const uint32_t es = (uint32_t)((uint64_t)colt * (uint32_t)(NT3 / W) % p.M);
     const double2 tb0 = p.tw.lo[eb & p.tw.mask], tb1 = p.tw.hi[eb >> p.tw.shift];
     const double2 ts0 = p.tw.lo[es & p.tw.mask], ts1 = p.tw.hi[es >> p.tw.shift];
     {
         double2 v[PER];
 #pragma unroll
         for (int q = 0; q < PER; q++) {
-            const int e = tid + q * NT;
-            if (L1 * W % NT == 0 || e < L1 * W) v[q] = p.za[(size_t)(e / W) * L2 + colt];
+            const int e = tid + q * NT3;
+            if (L1 * W % NT3 == 0 || e < L1 * W) v[q] = p.za[(size_t)(e / W) * L2 + colt];
         }
         // inverse inter-pass twiddles exp(+2 pi i col k1 / M)
         TwSeq<PER> tws;
         tws.init(cconj(cmul(tb0, tb1)), cconj(cmul(ts0, ts1)));
 #pragma unroll
         for (int q = 0; q < PER; q++) {
-            const int e = tid + q * NT;
-            if (L1 * W % NT == 0 || e < L1 * W) tile[pidx(e)] = cmul(v[q], tws.at(q));
+            const int e = tid + q * NT3;
+            if (L1 * W % NT3 == 0 || e < L1 * W) tile[pidx(e)] = cmul(v[q], tws.at(q));
         }
     }
     __syncthreads();
-    tile_fft<L1, W, NT, true, true>(tile, twl);
+    tile_fft<L1, W, NT3, true, true>(tile, twl);
 #pragma unroll
     for (int q = 0; q < PER; q++) {
-        const int e = threadIdx.x + q * NT;
-        if (L1 * W % NT == 0 || e < L1 * W) p.za[(size_t)(e / W) * L2 + c0 + e % W] = tile[pidx(e)];
+        const int e = threadIdx.x + q * NT3;
+        if (L1 * W % NT3 == 0 || e < L1 * W) p.za[(size_t)(e / W) * L2 + c0 + e % W] = tile[pidx(e)];
     }
 }
 
@@ -891,7 +902,6 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
     __shared__ double sGD[NW], sGA[NW];
     __shared__ uint32_t sGF;
     __shared__ double s_edge[K4_HALO + 1];
-    uint16_t* sd = reinterpret_cast<uint16_t*>(sq);  // digits reuse the q staging area
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const double* q = reinterpret_cast<const double*>(p.za);
 
@@ -1007,26 +1017,69 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
         if (ih >= i0 && ih < i0 + DPT) c[ih - i0] += 1ll << (dm1 - ih * (uint64_t)b);
     }
 
-    // carry function of this thread's digits: digit sweep with carry 0
-    const int64_t mask = (1ll << b) - 1;
-    int64_t carry = 0;
-    unsigned __int128 l = 0;
+    // S = sum_i c_i 2^(ib).  This workgroup's DPW coefficients start in its
+    // LPW = DPW b / 64 limbs of S (S limbs g LPW ..), limb j taking the c_i
+    // that start in bits [64 j, 64 j + 64):  T_j = sum c_i 2^(ib - 64j), a
+    // signed 128-bit value whose high half carries into limb j + 1.
+    int64_t* sc = reinterpret_cast<int64_t*>(sq);  // coefficients reuse the q staging area
+    __syncthreads();
 #pragma unroll
-    for (int t = 0; t < DPT; t++) {
-        int64_t sv = c[t] + carry;
-        l |= (unsigned __int128)(uint64_t)(sv & mask) << (t * b);
-        carry = sv >> b;
+    for (int t = 0; t < DPT; t++) sc[tid * DPT + t] = c[t];
+    __syncthreads();
+    const int LPW = DPW / 64 * b;
+    // limbs per thread: lpt or lpt + 1 (threads below ex), at most MLPT
+    constexpr int MLPT = (DPW / 64 * 16 + NT4 - 1) / NT4;
+    static_assert(DPW % 64 == 0 && DPW / 64 * 8 >= NT4, "every thread holds a limb for b >= 8");
+    const int lpt = LPW / NT4, ex = LPW % NT4;
+    const int j0 = tid * lpt + (tid < ex ? tid : ex);
+    const int nl = lpt + (tid < ex ? 1 : 0);
+    uint64_t tlo[MLPT];
+    int64_t thi[MLPT];
+    CarryF fl[MLPT];
+#pragma unroll
+    for (int k = 0; k < MLPT; k++) {
+        tlo[k] = 0;
+        thi[k] = 0;
+        fl[k] = CarryF{0, INT64_MAX};
+        if (k < nl) {
+            const int j = j0 + k;
+            const int ia = (64 * j + b - 1) / b, ib = (64 * (j + 1) + b - 1) / b;
+#pragma unroll
+            for (int u = 0; u < (64 + 7) / 8 + 1; u++) {
+                const int i = ia + u;
+                if (i < ib) {
+                    const int64_t cv = sc[i];
+                    const int sh = i * b - 64 * j;
+                    const uint64_t plo = (uint64_t)cv << sh;
+                    const int64_t phi = sh ? cv >> (64 - sh) : (cv >> 63);
+                    const uint64_t nlo = tlo[k] + plo;
+                    thi[k] += phi + (nlo < plo ? 1 : 0);
+                    tlo[k] = nlo;
+                }
+            }
+            // carry out of limb j: floor((T_j + cin) / 2^64) = A + [cin >= T]
+            if (tlo[k] >= (1ull << 63)) {
+                fl[k].A = thi[k];
+                fl[k].T = tlo[k] == (1ull << 63) ? INT64_MAX : (int64_t)(0 - tlo[k]);
+            } else {
+                fl[k].A = thi[k] - 1;
+                fl[k].T = -(int64_t)tlo[k];
+            }
+            // every carry is below 2^57 in magnitude (|c_i| < 2^51, at most
+            // 9 per limb), so a threshold beyond that decides the carry
+            // alone: make such functions constant (T = INT64_MAX)
+            if (fl[k].T > K4_CMAX) {
+                fl[k].T = INT64_MAX;
+            } else if (fl[k].T < -K4_CMAX) {
+                fl[k].A += 1;
+                fl[k].T = INT64_MAX;
+            }
+        }
     }
-    const int BT = DPT * b;
-    CarryF f;
-    if (l < ((unsigned __int128)1 << (BT - 1))) {
-        f.A = carry - 1;
-        f.T = l > (unsigned __int128)INT64_MAX ? INT64_MIN : -(int64_t)(uint64_t)l;
-    } else {
-        unsigned __int128 t = ((unsigned __int128)1 << BT) - l;
-        f.A = carry;
-        f.T = t > (unsigned __int128)INT64_MAX ? INT64_MAX : (int64_t)(uint64_t)t;
-    }
+    CarryF f = fl[0];
+#pragma unroll
+    for (int k = 1; k < MLPT; k++)
+        if (k < nl) f = compose(f, fl[k]);
 
     // inclusive scan of carry functions: within each wave by shuffles, then
     // across the NW waves through LDS
@@ -1098,7 +1151,9 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
                 r.A = __shfl(r.A, 0);
                 r.T = __shfl(r.T, 0);
                 const CarryF tot = have_acc ? compose(r, acc) : r;
-                if (any_incl) {
+                // done at an inclusive record, or as soon as the carry no
+                // longer depends on what lies further back (constant function)
+                if (any_incl || tot.T == INT64_MAX) {
                     cin = apply(tot, 0);
                     break;
                 }
@@ -1115,34 +1170,35 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
     }
     __syncthreads();
 
-    // final digits with the true carry-in
+    // limb values with the true carry-in (the look-back ended with a
+    // barrier, so every read of sc is done and sS may reuse the space)
     const int64_t cwg = s_cin;
-    carry = have_excl ? apply(excl, cwg) : cwg;
+    int64_t cin = have_excl ? apply(excl, cwg) : cwg;
+    uint64_t* sS = reinterpret_cast<uint64_t*>(sq);
 #pragma unroll
-    for (int t = 0; t < DPT; t++) {
-        int64_t sv = c[t] + carry;
-        sd[tid * DPT + t] = (uint16_t)(sv & mask);
-        carry = sv >> b;
+    for (int k = 0; k < MLPT; k++) {
+        if (k < nl) {
+            sS[j0 + k] = tlo[k] + (uint64_t)cin;
+            cin = apply(fl[k], cin);
+        }
     }
     __syncthreads();
 
-    // extraction: output bit j = bit (j + off) of S
-    const int64_t sb0 = (int64_t)(base * b), sb1 = (int64_t)((base + DPW) * b);
+    // extraction: output bit j = bit (j + off) of S; output limbs that
+    // straddle two workgroups' limbs are OR-ed together (K1 zeroed them)
+    const int64_t sb0 = (int64_t)g * LPW * 64, sb1 = sb0 + (int64_t)LPW * 64;
     const int64_t ob0 = sb0 - (int64_t)p.off, ob1 = sb1 - (int64_t)p.off;
     const int64_t lo_o = ob0 > 0 ? ob0 : 0;
     const int64_t hi_o = ob1 < (int64_t)p.out_bits ? ob1 : (int64_t)p.out_bits;
     if (hi_o <= lo_o) return;
     const int64_t l0 = lo_o >> 6, l1 = (hi_o - 1) >> 6;
+    const int r = (int)(p.off & 63);
     for (int64_t li = l0 + tid; li <= l1; li += NT4) {
         const int64_t sl = li * 64 + (int64_t)p.off;  // S bit of output bit 64 li
-        const int64_t a = sl > sb0 ? sl : sb0;
-        const int64_t z = sl + 64 < sb1 ? sl + 64 : sb1;
+        const int64_t jl = (sl >> 6) - (int64_t)g * LPW;
         uint64_t val = 0;
-        for (int64_t i = a / b; i * b < z; i++) {
-            const uint64_t dv = sd[i - (int64_t)base];
-            const int64_t sh = i * b - sl;
-            val |= sh >= 0 ? (dv << sh) : (dv >> (-sh));
-        }
+        if (jl >= 0 && jl < LPW) val |= sS[jl] >> r;
+        if (r && jl + 1 >= 0 && jl + 1 < LPW) val |= sS[jl + 1] << (64 - r);
         if ((uint64_t)(li + 1) * 64 > p.out_bits) {
             const int keep = (int)(p.out_bits - (uint64_t)li * 64);
             val &= (1ull << keep) - 1;

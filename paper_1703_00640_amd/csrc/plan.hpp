@@ -19,7 +19,13 @@ constexpr int B_TRUNC = 11;          // digit size of the truncated products (8.
 constexpr int B_FULL = 16;           // digit size of the full product
 constexpr uint64_t TRUNC_MIN_BITS = 1025;  // below: full product + extraction
 constexpr uint32_t L2_MAX = 1024, L1_MAX = 4096, LM_MAX = 256;
-constexpr int DPW_HOST = 7 * 1024;   // digits per K4 workgroup
+#ifndef TM_NT4
+#define TM_NT4 512
+#endif
+#ifndef TM_DPT
+#define TM_DPT 8
+#endif
+constexpr int DPW_HOST = TM_DPT * TM_NT4;  // coefficients per K4 workgroup
 
 struct Plan {
     int req_kind = 0;   // requested tm_kind

@@ -132,7 +132,7 @@ bool launch_k3(uint32_t L1, const KParams& p, hipStream_t s)
 {
     switch (L1) {
 #define X(V) \
-    case V: hipLaunchKernelGGL((k3_col_inverse<V, w_for(V)>), dim3(p.R / w_for(V)), dim3(NT), 0, s, p); return true;
+    case V: hipLaunchKernelGGL((k3_col_inverse<V, w_for(V)>), dim3(p.R / w_for(V)), dim3(NT3), 0, s, p); return true;
         TM_L1_LIST(X)
 #undef X
     }
