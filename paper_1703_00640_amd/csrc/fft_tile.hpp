@@ -2,10 +2,11 @@
 //
 // This is the building block of the Convolution step (Section 2.1: real
 // FFTs, pointwise product, inverse FFT).  A tile holds NB independent
-// sequences of length P; a Stockham autosort schedule of radix-3/4/8/2
-// stages transforms all of them in place, one LDS round trip per stage.
-// Stage twiddles come from an LDS copy of exp(-2 pi i e / P), e < P, so no
-// stage waits on global memory.
+// sequences of length P; a Stockham autosort schedule of radix-3/16/8/4/2
+// stages transforms all of them in place, one LDS round trip per stage
+// (radix 16 runs as 4 x 4 in registers).  Each butterfly reads one stage
+// twiddle from an LDS copy of exp(-2 pi i e / P) and forms the others as
+// its powers, so no stage waits on global memory.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -126,19 +127,82 @@ __device__ __forceinline__ void dft8(double2* v)
     }
 }
 
+// v * exp(-+2 pi i M / 16) with the trivial factors done without products
+template <int M, bool INV>
+__device__ __forceinline__ double2 tw16(double2 v)
+{
+    constexpr int m = M & 15;
+    constexpr double C1 = 0.92387953251128675613;  // cos(pi/8)
+    constexpr double S1 = 0.38268343236508977173;  // sin(pi/8)
+    constexpr double H = 0.70710678118654752440;   // cos(pi/4)
+    constexpr double cs[16] = {1, C1, H, S1, 0, -S1, -H, -C1, -1, -C1, -H, -S1, 0, S1, H, C1};
+    constexpr double cc = cs[m], sn = cs[(m + 12) & 15];  // cos(2 pi m/16), sin(2 pi m/16)
+    if constexpr (m == 0) return v;
+    else if constexpr (m == 4) return mul_mi<INV>(v);
+    else if constexpr (m == 8) return make_double2(-v.x, -v.y);
+    else if constexpr (m == 12) return mul_mi<!INV>(v);
+    else {
+        // forward: (cc - i sn) v; inverse: (cc + i sn) v
+        const double s = INV ? sn : -sn;
+        return make_double2(fma(cc, v.x, -s * v.y), fma(cc, v.y, s * v.x));
+    }
+}
+
+// 16-point DFT as 4 x 4: inner DFT4 over n2 (n = n1 + 4 n2), twiddles
+// w16^(n1 k2), outer DFT4 over n1; output index k2 + 4 k1.
+template <bool INV>
+__device__ __forceinline__ void dft16(double2* v)
+{
+    double2 y[4][4];
+#pragma unroll
+    for (int n1 = 0; n1 < 4; n1++) {
+        double2 t[4] = {v[n1], v[n1 + 4], v[n1 + 8], v[n1 + 12]};
+        dft4<INV>(t);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; k2++) y[n1][k2] = t[k2];
+    }
+    y[1][1] = tw16<1, INV>(y[1][1]);
+    y[1][2] = tw16<2, INV>(y[1][2]);
+    y[1][3] = tw16<3, INV>(y[1][3]);
+    y[2][1] = tw16<2, INV>(y[2][1]);
+    y[2][2] = tw16<4, INV>(y[2][2]);
+    y[2][3] = tw16<6, INV>(y[2][3]);
+    y[3][1] = tw16<3, INV>(y[3][1]);
+    y[3][2] = tw16<6, INV>(y[3][2]);
+    y[3][3] = tw16<9, INV>(y[3][3]);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; k2++) {
+        double2 t[4] = {y[0][k2], y[1][k2], y[2][k2], y[3][k2]};
+        dft4<INV>(t);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; k1++) v[k2 + 4 * k1] = t[k1];
+    }
+}
+
 template <int R, bool INV>
 __device__ __forceinline__ void dftR(double2* v)
 {
     if constexpr (R == 2) dft2<INV>(v);
     else if constexpr (R == 3) dft3<INV>(v);
     else if constexpr (R == 4) dft4<INV>(v);
-    else dft8<INV>(v);
+    else if constexpr (R == 8) dft8<INV>(v);
+    else dft16<INV>(v);
+}
+
+// w^1 .. w^(R-1) from w: each power is one product of two earlier ones
+// (error grows with log2 r, not r)
+template <int R>
+__device__ __forceinline__ void tw_powers(double2 w, double2* pw)
+{
+    pw[1] = w;
+#pragma unroll
+    for (int r = 2; r < R; r++) pw[r] = cmul(pw[r / 2], pw[r - r / 2]);
 }
 
 // radix of the next stage given the remaining length
 constexpr int pick_radix(int rem)
 {
-    return rem % 3 == 0 ? 3 : rem == 16 ? 4 : rem % 8 == 0 ? 8 : rem % 4 == 0 ? 4 : 2;
+    return rem % 3 == 0 ? 3 : rem % 16 == 0 ? 16 : rem % 8 == 0 ? 8 : rem % 4 == 0 ? 4 : 2;
 }
 
 // LDS tiles are padded by one element after every 16, which spreads the
@@ -198,11 +262,12 @@ __device__ __forceinline__ void fft_stage(double2* buf, const double2* twl)
             const int j = jj[q];
             const int k = (NS == 1) ? 0 : j % NS;
             if (NS > 1 && k != 0) {
+                // one table read per butterfly, the other twiddles as powers
+                const double2 w1 = tw_half<P>(twl, k * ESTEP);
+                double2 pw[R];
+                tw_powers<R>(INV ? cconj(w1) : w1, pw);
 #pragma unroll
-                for (int r = 1; r < R; r++) {
-                    const double2 w = tw_half<P>(twl, (r * k) * ESTEP);
-                    v[q][r] = cmul(v[q][r], INV ? cconj(w) : w);
-                }
+                for (int r = 1; r < R; r++) v[q][r] = cmul(v[q][r], pw[r]);
             }
             dftR<R, INV>(v[q]);
             const int out = (j - k) * R + k;

@@ -623,7 +623,7 @@ __global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
     tile_fft<L2, 4, NT, false, false, L2>(rows, twl);
 
     constexpr int PER = (2 * L2 + NT - 1) / NT;
-    const double2 wrow[2] = {cmul(wr0a, wr0b), cmul(wr1a, wr1b)};
+    const double2 wrow0 = cmul(wr0a, wr0b), wrow1 = cmul(wr1a, wr1b);
     double2 qv[PER];
 #pragma unroll
     for (int t = 0; t < PER; t++) {
@@ -634,7 +634,7 @@ __global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
             const int mr = 1 - pr;
             qv[t] = pointwise_bin(rows[pidx((2 * pr) * L2 + k2)], rows[pidx((2 * mr) * L2 + mk2)],
                                   rows[pidx((2 * pr + 1) * L2 + k2)], rows[pidx((2 * mr + 1) * L2 + mk2)],
-                                  cmul(wrow[pr], tw_half<L2>(twl, k2)));
+                                  cmul(pr ? wrow1 : wrow0, tw_half<L2>(twl, k2)));
         }
     }
     __syncthreads();
