@@ -41,7 +41,18 @@ constexpr int DPT = TM_DPT;     // coefficients per thread in K4
 constexpr int NT4 = TM_NT4;     // threads per K4 workgroup
 constexpr int NT3 = TM_NT3;     // threads per K3 workgroup
 constexpr int DPW = DPT * NT4;  // coefficients per workgroup in K4
-constexpr int TILE = 4096;      // complex elements per column tile (64 KiB)
+#ifndef TM_TILE1
+#define TM_TILE1 4096
+#endif
+#ifndef TM_TILE3
+#define TM_TILE3 4096
+#endif
+#ifndef TM_NT1
+#define TM_NT1 256
+#endif
+constexpr int TILE1 = TM_TILE1;  // complex elements per K1 column tile
+constexpr int TILE3 = TM_TILE3;  // complex elements per K3 column tile
+constexpr int NT1 = TM_NT1;      // threads per K1 workgroup
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 constexpr int K4_HALO = 32;        // q values staged below a K4 workgroup's range
 constexpr int64_t K4_CMAX = 1ll << 57;  // bound on the carries between limbs
@@ -403,16 +414,16 @@ __device__ __forceinline__ void row_map_edge(const KParams& p, uint32_t m0, doub
 // (M = L1 R, R = Lm L2; element (k1, col) is point m = k1 R + col).
 // B: compile-time digit size (0: runtime p.b).
 template <int L1, int W, int KIND, int B>
-__global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
+__global__ __launch_bounds__(NT1) void k1_split_map_col(KParams p)
 {
-    static_assert(L1 * W <= TILE, "tile too large");
-    constexpr int PER = (L1 * W + NT - 1) / NT;
+    static_assert(L1 * W <= TILE1, "tile too large");
+    constexpr int PER = (L1 * W + NT1 - 1) / NT1;
     constexpr int LB = k1_lb(KIND, B), LO = LB - 1, ND = k1_nd(W, KIND, B), NLW = k1_nlw(ND, B);
     constexpr int TE = padded(L1 * W);
     // limb windows staged in the tile area when they fit
     constexpr bool STAGE = L1 * NLW * 8 <= TE * 16;
     static_assert(STAGE || B == 0, "compile-time digit sizes need staged limbs");
-    constexpr int RPT = (L1 + NT - 1) / NT;
+    constexpr int RPT = (L1 + NT1 - 1) / NT1;
     __shared__ double2 tile[TE];
     __shared__ double2 twl[twl_size(L1)];
     __shared__ double s_FN;
@@ -423,28 +434,28 @@ __global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
     const uint32_t c0 = xcd_tile(blockIdx.x, gridDim.x) * W;
     const int tid = threadIdx.x;
 
-    load_twl<L1, NT>(twl, p.tw1);
+    load_twl<L1, NT1>(twl, p.tw1);
     // inter-pass twiddles exp(-2 pi i col k1 / M): this thread's elements
-    // share col = c0 + tid % W and step k1 by NT / W
-    static_assert(NT % W == 0, "W must divide NT");
+    // share col = c0 + tid % W and step k1 by NT1 / W
+    static_assert(NT1 % W == 0, "W must divide NT1");
     const uint32_t colt = c0 + tid % W;
     const uint32_t eb = (uint32_t)((uint64_t)colt * (uint32_t)(tid / W) % p.M);
-    const uint32_t es = (uint32_t)((uint64_t)colt * (uint32_t)(NT / W) % p.M);
+    const uint32_t es = (uint32_t)((uint64_t)colt * (uint32_t)(NT1 / W) % p.M);
     const double2 tb0 = p.tw.lo[eb & p.tw.mask], tb1 = p.tw.hi[eb >> p.tw.shift];
     const double2 ts0 = p.tw.lo[es & p.tw.mask], ts1 = p.tw.hi[es >> p.tw.shift];
-    if (op == 0) clear_state(p, blockIdx.x * NT + tid, gridDim.x * NT);
+    if (op == 0) clear_state(p, blockIdx.x * NT1 + tid, gridDim.x * NT1);
     if (KIND == K_HI && tid == 0) {
         s_FN = (double)bal_digit(p, x, p.N, p.digits, true);
         if (blockIdx.x == 0) p.theta[op] = hi_theta(p, x);
     }
     if constexpr (STAGE) {
         uint64_t* slimb = reinterpret_cast<uint64_t*>(tile);
-        constexpr int PL = (L1 * NLW + NT - 1) / NT;
+        constexpr int PL = (L1 * NLW + NT1 - 1) / NT1;
         uint64_t lv[PL];
 #pragma unroll
         for (int q = 0; q < PL; q++) {
-            const int e = tid + q * NT;
-            if (L1 * NLW % NT == 0 || e < L1 * NLW) {
+            const int e = tid + q * NT1;
+            if (L1 * NLW % NT1 == 0 || e < L1 * NLW) {
                 const int row = e / NLW, i = e % NLW;
                 int64_t l0;
                 int rel0;
@@ -454,8 +465,8 @@ __global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
         }
 #pragma unroll
         for (int q = 0; q < PL; q++) {
-            const int e = tid + q * NT;
-            if (L1 * NLW % NT == 0 || e < L1 * NLW) slimb[e] = lv[q];
+            const int e = tid + q * NT1;
+            if (L1 * NLW % NT1 == 0 || e < L1 * NLW) slimb[e] = lv[q];
         }
     }
     __syncthreads();
@@ -467,8 +478,8 @@ __global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
     double2 g[RPT][W];
 #pragma unroll
     for (int rr = 0; rr < RPT; rr++) {
-        const int j1 = tid + rr * NT;
-        if (L1 % NT == 0 || j1 < L1) {
+        const int j1 = tid + rr * NT1;
+        if (L1 % NT1 == 0 || j1 < L1) {
             const uint32_t m0 = (uint32_t)j1 * L2 + c0;
             const int64_t kf = 2 * (int64_t)m0 - LO;
             const bool fast = kf >= kf_min && (KIND != K_FULL || kf + ND <= top);
@@ -508,20 +519,20 @@ __global__ __launch_bounds__(NT) void k1_split_map_col(KParams p)
     if constexpr (STAGE) __syncthreads();
 #pragma unroll
     for (int rr = 0; rr < RPT; rr++) {
-        const int j1 = tid + rr * NT;
-        if (L1 % NT == 0 || j1 < L1) {
+        const int j1 = tid + rr * NT1;
+        if (L1 % NT1 == 0 || j1 < L1) {
 #pragma unroll
             for (int c = 0; c < W; c++) tile[pidx(j1 * W + c)] = g[rr][c];
         }
     }
     __syncthreads();
-    tile_fft<L1, W, NT, false, true>(tile, twl);
+    tile_fft<L1, W, NT1, false, true>(tile, twl);
     TwSeq<PER> tws;
     tws.init(cmul(tb0, tb1), cmul(ts0, ts1));
 #pragma unroll
     for (int q = 0; q < PER; q++) {
-        const int e = tid + q * NT;
-        if (L1 * W % NT == 0 || e < L1 * W) {
+        const int e = tid + q * NT1;
+        if (L1 * W % NT1 == 0 || e < L1 * W) {
             const int k1 = e / W;
             dst[(size_t)k1 * L2 + colt] = cmul(tile[pidx(e)], tws.at(q));
         }

@@ -89,13 +89,16 @@ tm_status get_twiddles(uint64_t M, uint32_t L1, uint32_t Lm, uint32_t L2, hipStr
 
 // ------------------------------------------------------------ dispatch
 
-constexpr int w_for(int L1)
+// column tile width: the largest power of two W <= 8 with L1 W <= tile
+constexpr int w_for(int L1, int tile)
 {
-    int lim = TILE / L1 < 8 ? TILE / L1 : 8;
+    int lim = tile / L1 < 8 ? tile / L1 : 8;
     int w = 1;
     while (w * 2 <= lim) w *= 2;
     return w;
 }
+constexpr int w1_for(int L1) { return w_for(L1, TILE1); }
+constexpr int w3_for(int L1) { return w_for(L1, TILE3); }
 
 #define TM_L1_LIST(X) \
     X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) \
@@ -115,7 +118,7 @@ bool launch_k1_b(uint32_t L1, const KParams& p, hipStream_t s)
 {
     switch (L1) {
 #define X(V) \
-    case V: hipLaunchKernelGGL((k1_split_map_col<V, w_for(V), KIND, B>), dim3(p.R / w_for(V), 2), dim3(NT), 0, s, p); return true;
+    case V: hipLaunchKernelGGL((k1_split_map_col<V, w1_for(V), KIND, B>), dim3(p.R / w1_for(V), 2), dim3(NT1), 0, s, p); return true;
         TM_L1_LIST(X)
 #undef X
     }
@@ -132,7 +135,7 @@ bool launch_k3(uint32_t L1, const KParams& p, hipStream_t s)
 {
     switch (L1) {
 #define X(V) \
-    case V: hipLaunchKernelGGL((k3_col_inverse<V, w_for(V)>), dim3(p.R / w_for(V)), dim3(NT3), 0, s, p); return true;
+    case V: hipLaunchKernelGGL((k3_col_inverse<V, w3_for(V)>), dim3(p.R / w3_for(V)), dim3(NT3), 0, s, p); return true;
         TM_L1_LIST(X)
 #undef X
     }
