@@ -216,6 +216,18 @@ def main():
         torch.cuda.synchronize()
         per[k] = a.elapsed_time(b) / args.steps
 
+    # squaring (u == v: one forward transform), same loop shape
+    per_sq = {}
+    for k in kinds:
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.steps):
+            tm.mul(k, du, du, n, out=outs[k], workspace=ws[k], stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        per_sq[k] = a.elapsed_time(b) / args.steps
+
     # per kernel, HIP events recorded by the library between its launches
     stage = {k: {} for k in kinds}
     reps = max(5, min(args.steps, 20))
@@ -260,6 +272,7 @@ def main():
         "mbit_s": {k: round(n / (per[k] * 1e-3) / 1e6, 2) for k in kinds},
         "ratio_lo_full": round(per["lo"] / per["full"], 4),
         "ratio_hi_full": round(per["hi"] / per["full"], 4),
+        "square_ms": {k: round(per_sq[k], 5) for k in kinds},
         "stage_ms": {k: {s: round(t, 5) for s, t in stage[k].items()} for k in kinds},
         "guard_max_dist": {k: gd[k]["max_dist"] for k in kinds},
         "guard_flags": {k: gd[k]["flags"] for k in kinds},

@@ -16,7 +16,8 @@
  * - Outputs: low and high product -> L limbs, bits >= n cleared; full
  *   product -> 2L limbs.
  * - The caller owns u, v, w and the workspace.  w must not overlap u, v or
- *   the workspace; u == v (squaring) is allowed.  Workspace size comes from
+ *   the workspace.  u == v (the same pointer) computes a square with one
+ *   forward transform instead of two.  Workspace size comes from
  *   tm_workspace_bytes() and must be at least that many bytes, 256-byte
  *   aligned.
  * - All calls are asynchronous on the given HIP stream (NULL = default

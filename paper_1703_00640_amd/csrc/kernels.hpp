@@ -161,18 +161,6 @@ __device__ __forceinline__ double coef_back(const KParams& p, uint32_t k, int r)
     return v;
 }
 
-// Top digit F_N of the high-product split and theta = rho^-N F(rho) with
-// rho ~ 2^b (Remark on Newton's method): theta = sum_j 2^(-jb) F_(N-j).
-__device__ __forceinline__ double hi_theta(const KParams& p, const uint64_t* x)
-{
-    double t = 0.0;
-    for (int j = 0; j <= (int)p.jmax && j <= (int)p.N; j++) {
-        double f = (double)bal_digit(p, x, (int64_t)p.N - j, p.digits, true);
-        t += ldexp(f, -j * p.b);
-    }
-    return t;
-}
-
 // Clear the per-call state that K4 accumulates into (output limbs for the
 // partial-limb OR, guard, look-back records, ticket).  Done by K1.
 __device__ __forceinline__ void clear_state(const KParams& p, uint32_t gid, uint32_t gsize)
@@ -426,7 +414,7 @@ __global__ __launch_bounds__(NT1) void k1_split_map_col(KParams p)
     constexpr int RPT = (L1 + NT1 - 1) / NT1;
     __shared__ double2 tile[TE];
     __shared__ double2 twl[twl_size(L1)];
-    __shared__ double s_FN;
+    __shared__ double s_th[LMAX + 8];  // terms of theta (high product, tile 0)
     const int op = blockIdx.y;
     const uint64_t* x = op ? p.v : p.u;
     double2* dst = op ? p.zb : p.za;
@@ -444,10 +432,8 @@ __global__ __launch_bounds__(NT1) void k1_split_map_col(KParams p)
     const double2 tb0 = p.tw.lo[eb & p.tw.mask], tb1 = p.tw.hi[eb >> p.tw.shift];
     const double2 ts0 = p.tw.lo[es & p.tw.mask], ts1 = p.tw.hi[es >> p.tw.shift];
     if (op == 0) clear_state(p, blockIdx.x * NT1 + tid, gridDim.x * NT1);
-    if (KIND == K_HI && tid == 0) {
-        s_FN = (double)bal_digit(p, x, p.N, p.digits, true);
-        if (blockIdx.x == 0) p.theta[op] = hi_theta(p, x);
-    }
+    if (KIND == K_HI && blockIdx.x == 0 && tid <= (int)p.jmax && tid <= (int)p.N)
+        s_th[tid] = ldexp((double)bal_digit(p, x, (int64_t)p.N - tid, p.digits, true), -tid * p.b);
     if constexpr (STAGE) {
         uint64_t* slimb = reinterpret_cast<uint64_t*>(tile);
         constexpr int PL = (L1 * NLW + NT1 - 1) / NT1;
@@ -470,7 +456,13 @@ __global__ __launch_bounds__(NT1) void k1_split_map_col(KParams p)
         }
     }
     __syncthreads();
-    const double FN = KIND == K_HI ? s_FN : 0.0;
+    if (KIND == K_HI && blockIdx.x == 0 && tid == 0) {
+        // theta = rho^-N F(rho), rho ~ 2^b: sum_j 2^(-jb) F_(N-j), j <= jmax
+        double th = 0.0;
+        for (int j = 0; j <= (int)p.jmax && j <= (int)p.N; j++) th += s_th[j];
+        p.theta[op] = th;
+        if (gridDim.y == 1) p.theta[1] = th;  // squaring: theta_V = theta_U
+    }
     // rows away from index 0 (and, for the full product, from the top digit)
     // take the fast path; the others the term-by-term one
     const int64_t kf_min = KIND == K_HI ? (int64_t)p.jmax : 0;
@@ -511,6 +503,7 @@ __global__ __launch_bounds__(NT1) void k1_split_map_col(KParams p)
                     for (int c = 0; c < W; c++)
                         g[rr][c] = make_double2((double)d[2 * c], (double)d[2 * c + 1]);
                 } else {
+                    const double FN = KIND == K_HI ? (double)bal_digit(p, x, p.N, p.digits, true) : 0.0;
                     row_map_edge<W, KIND, ND, LB>(p, m0, FN, d, g[rr]);
                 }
             }
@@ -835,37 +828,59 @@ __device__ __forceinline__ double wave_max(double v)
 //         H_i = sum_r delta_{i-r,r} W_(i-r) (r <= i) + sum_j 2^(-jb)
 //         sum_{r > i-j} delta_{N+i-j-r,r} W_(N+i-j-r)  (X^(N+s) = sum_j
 //         2^(-jb) X^(s+j) mod C)
-// The sums use the unnormalised q = M W.  back_edge_* evaluate them term by
+// The sums use the unnormalised q = M W.  edge_part / edge_sum evaluate them term by
 // term for the indices next to the wrap (i < K4_HALO) and the top index
 // i = N of the high product; all other indices use back_chain.
+// Parts of the sum at index i next to the wrap (workgroup 0: o = i), one
+// per thread; edge_sum combines them in a fixed order.
+//   low:  part 0 = sum_r beta_{(i-r) mod N, r} q_((i-r) mod N),
+//         part 1 = sum_{r>=i} beta_{N+i-1-r,r} q_(N+i-1-r)  (1 <= i < lam)
+//   high: part K4_EP-1 = sum_{r<=i} delta_{i-r,r} q_(i-r),
+//         part j (j <= min(i, jmax)) = sum_{r>i-j} delta_{N+i-j-r,r} q_(N+i-j-r)
+constexpr int K4_EP = 12;  // parts per index (jmax + 2 <= 12 for b >= 8)
 template <int KIND>
-__device__ double back_edge_sum(const KParams& p, const double* sq, uint32_t i)
+__device__ double edge_part(const KParams& p, const double* sq, uint32_t i, int part)
 {
-    // unwrapped part: sum_{r <= i} coef_{i-r,r} q_(i-r)   (workgroup 0: o = i)
     const int o = (int)i + K4_HALO;
     double s = 0.0;
-    for (int r = 0; r < p.lam && r <= (int)i; r++) s = fma(coef_back<KIND>(p, i - r, r), sq[o - r], s);
     if (KIND == K_LO) {
-        for (int r = (int)i + 1; r < p.lam; r++) s = fma(coef_back<KIND>(p, p.N + i - r, r), sq[o - r], s);
-        if (i >= 1 && i < (uint32_t)p.lam) {
-            double t = 0.0;
+        if (part == 0) {
+            for (int r = 0; r < p.lam && r <= (int)i; r++)
+                s = fma(coef_back<KIND>(p, i - r, r), sq[o - r], s);
+            for (int r = (int)i + 1; r < p.lam; r++)
+                s = fma(coef_back<KIND>(p, p.N + i - r, r), sq[o - r], s);
+        } else if (part == 1 && i >= 1 && i < (uint32_t)p.lam) {
             for (int r = (int)i; r < p.lam; r++)
-                t = fma(coef_back<KIND>(p, p.N + i - 1 - r, r), sq[o - 1 - r], t);
-            s = fma(-ldexp(1.0, -p.b), t, s);
+                s = fma(coef_back<KIND>(p, p.N + i - 1 - r, r), sq[o - 1 - r], s);
         }
     } else {
-        for (int j = 0; j <= (int)i && j <= (int)p.jmax; j++) {
-            double t = 0.0;
+        if (part == K4_EP - 1) {
+            for (int r = 0; r < p.lam && r <= (int)i; r++)
+                s = fma(coef_back<KIND>(p, i - r, r), sq[o - r], s);
+        } else if (part <= (int)i && part <= (int)p.jmax) {
+            const int j = part;
             for (int r = (int)i - j + 1; r < p.lam; r++)
-                t = fma(coef_back<KIND>(p, p.N + i - j - r, r), sq[o - j - r], t);
-            s = fma(ldexp(1.0, -j * p.b), t, s);
+                s = fma(coef_back<KIND>(p, p.N + i - j - r, r), sq[o - j - r], s);
         }
     }
     return s;
 }
 
+template <int KIND>
+__device__ __forceinline__ double edge_sum(const KParams& p, const double* ep, uint32_t i)
+{
+    if (KIND == K_LO) {
+        double s = ep[0];
+        if (i >= 1 && i < (uint32_t)p.lam) s = fma(-ldexp(1.0, -p.b), ep[1], s);
+        return s;
+    }
+    double s = ep[K4_EP - 1];
+    for (int j = 0; j <= (int)i && j <= (int)p.jmax; j++) s = fma(ldexp(1.0, -j * p.b), ep[j], s);
+    return s;
+}
+
 // x_i for i < K4_HALO (workgroup 0) from se[i + 1] = the sum of
-// back_edge_sum at index i (se[0] = 0: the index below 0).
+// edge_sum at index i (se[0] = 0: the index below 0).
 template <int KIND>
 __device__ __forceinline__ double back_edge(const KParams& p, const double* se, uint32_t i, double thW)
 {
@@ -913,6 +928,7 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
     __shared__ double sGD[NW], sGA[NW];
     __shared__ uint32_t sGF;
     __shared__ double s_edge[K4_HALO + 1];
+    __shared__ double sc_edge[K4_HALO * K4_EP];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const double* q = reinterpret_cast<const double*>(p.za);
 
@@ -962,8 +978,15 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
             }
         }
         if (base == 0) {
-            // indices next to the wrap, one sum per thread
-            if (tid <= K4_HALO) s_edge[tid] = tid ? back_edge_sum<KIND>(p, sq, (uint32_t)tid - 1) : 0.0;
+            // indices next to the wrap: parts spread over threads, then one
+            // fixed-order combination per index
+            static_assert(K4_HALO * K4_EP <= NT4, "edge parts need one thread each");
+            double* s_ep = reinterpret_cast<double*>(sc_edge);
+            if (tid < K4_HALO * K4_EP)
+                s_ep[tid] = edge_part<KIND>(p, sq, (uint32_t)(tid / K4_EP), tid % K4_EP);
+            __syncthreads();
+            if (tid <= K4_HALO)
+                s_edge[tid] = tid ? edge_sum<KIND>(p, s_ep + (tid - 1) * K4_EP, (uint32_t)tid - 1) : 0.0;
             __syncthreads();
 #pragma unroll
             for (int t = 0; t < DPT; t++)

@@ -118,7 +118,7 @@ bool launch_k1_b(uint32_t L1, const KParams& p, hipStream_t s)
 {
     switch (L1) {
 #define X(V) \
-    case V: hipLaunchKernelGGL((k1_split_map_col<V, w1_for(V), KIND, B>), dim3(p.R / w1_for(V), 2), dim3(NT1), 0, s, p); return true;
+    case V: hipLaunchKernelGGL((k1_split_map_col<V, w1_for(V), KIND, B>), dim3(p.R / w1_for(V), p.zb == p.za ? 1 : 2), dim3(NT1), 0, s, p); return true;
         TM_L1_LIST(X)
 #undef X
     }
@@ -163,7 +163,7 @@ template <bool INV>
 bool launch_mid(const KParams& p, hipStream_t s)
 {
     const int W = (int)p.L2 < w_mid((int)p.Lm) ? (int)p.L2 : w_mid((int)p.Lm);
-    dim3 g(p.L2 / W, p.L1, INV ? 1 : 2);
+    dim3 g(p.L2 / W, p.L1, INV || p.zb == p.za ? 1 : 2);
 #define MIDW(LM, WW) \
     if (p.Lm == LM && W == WW) { hipLaunchKernelGGL((k_mid_col<LM, WW, INV>), g, dim3(NT), 0, s, p); return true; }
 #define MID(LM) MIDW(LM, 16) MIDW(LM, 32) MIDW(LM, 64)
@@ -264,7 +264,8 @@ void fill_params(const Plan& P, const uint64_t* u, const uint64_t* v, uint64_t* 
     p.invM = 1.0 / (double)P.M;
     fill_series(P, p);
     p.za = reinterpret_cast<double2*>(base + P.o_za);
-    p.zb = reinterpret_cast<double2*>(base + P.o_zb);
+    // squaring (u == v): one forward transform, both spectra read from za
+    p.zb = u == v ? p.za : reinterpret_cast<double2*>(base + P.o_zb);
     p.status = reinterpret_cast<uint64_t*>(base + P.o_status);
     p.ticket = reinterpret_cast<uint32_t*>(base + P.o_ticket);
     p.guard = guard ? guard : reinterpret_cast<tm_guard*>(base + P.o_guard);

@@ -230,6 +230,29 @@ def test_forced_three_pass_split(monkeypatch, lm, n):
     check_all(u, v, n)
 
 
+@pytest.mark.parametrize("n,lm", [(65536, 0), (100003, 0), (65536, 4), (1 << 22, 0)])
+def test_squaring_one_transform(monkeypatch, n, lm):
+    """u == v (one pointer) takes the squaring path (one forward transform);
+    its products equal the oracle's square and, bit for bit, the products of
+    two distinct copies of u."""
+    if lm:
+        monkeypatch.setenv("TM_FORCE_LM", str(lm))
+    tm = _tm()
+    u, _ = inputs.operand_pair(n, 60)
+    say("[parity] squaring n=%d Lm=%s" % (n, tm.plan("lo", n)["Lm"]))
+    du = to_dev(u)
+    du2 = du.clone()
+    for kind in ("lo", "hi", "full"):
+        sq = to_host(tm.mul(kind, du, du, n))
+        two = to_host(tm.mul(kind, du, du2, n))
+        torch.cuda.synchronize()
+        assert np.array_equal(sq, two), "square differs from two-operand product (%s)" % kind
+    assert np.array_equal(to_host(tm.mul("full", du, du, n)), oracle.mul_full(u, u, n, 8))
+    assert np.array_equal(to_host(tm.mul("lo", du, du, n)), oracle.mul_lo(u, u, n, 8))
+    q, nz = oracle.mul_hi(u, u, n, 8)
+    assert oracle.hi_accepts(to_host(tm.mul("hi", du, du, n)), q, nz)
+
+
 def test_config_n2_26_parity():
     """n = 2^26 (three-pass split chosen automatically): lo, hi, full vs the
     oracle."""
