@@ -8,6 +8,9 @@ fixed seed), inputs resident in HBM.  Prints one JSON line with
 * per-kind time and Mbit/s, and the lo/full and hi/full time ratios;
 * roofline: algorithmic bytes / time of the dominant kernel, timed with HIP
   events on the launch stream, against the 8 TB/s HBM peak;
+* large_n: the same three products at n = 2^30 (the largest single
+  instance), per kind and per kernel, with each kernel's fraction of the HBM
+  peak;
 * serving: p50 / p99 latency and throughput of a mixed stream of requests
   (n from 2^12 to 2^22 bits, all three kinds) through the library's
   continuous-batching server, saturated and under Poisson arrivals;
@@ -104,6 +107,54 @@ def pmc_pass(n_bits):
     print("pmc pass done", flush=True)
 
 
+def large_n_bench(log2n, steps):
+    """The three products at one large size (n = 2^30 by default: the
+    largest single instance), per kind and per kernel, with each kernel's
+    algorithmic GB/s against the HBM peak."""
+    import torch
+    import paper_1703_00640_amd as tm
+    from paper_1703_00640_amd import inputs
+    n = 1 << log2n
+    L = n // 64
+    dev = torch.device("cuda:0")
+    u, v = inputs.operand_pair(n, 5)
+    du = torch.from_numpy(u.view(np.int64)).to(dev)
+    dv = torch.from_numpy(v.view(np.int64)).to(dev)
+    del u, v
+    stream = torch.cuda.current_stream(dev)
+    res = {"n_bits": n, "ms": {}, "stage_ms": {}, "stage_gb_s": {}, "hbm_frac": {}, "plans": {}}
+    for k in ("lo", "hi", "full"):
+        pl = tm.plan(k, n)
+        res["plans"][k] = {x: pl[x] for x in ("b", "lam", "N", "L1", "Lm", "L2")}
+        ws = torch.empty(pl["workspace_bytes"], dtype=torch.uint8, device=dev)
+        out = torch.empty(2 * L if k == "full" else L, dtype=torch.int64, device=dev)
+        for _ in range(2):
+            tm.mul(k, du, dv, n, out=out, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            tm.mul(k, du, dv, n, out=out, workspace=ws, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        res["ms"][k] = round(a.elapsed_time(b) / steps, 4)
+        acc = {}
+        for _ in range(steps):
+            for name, ms in tm.profile_stages(k, du, dv, n, out, ws, stream=stream):
+                acc.setdefault(name, []).append(ms)
+        nb = kernel_bytes(pl, n, k)
+        st = {name: float(np.median(vv)) for name, vv in acc.items()}
+        res["stage_ms"][k] = {nm: round(t, 4) for nm, t in st.items()}
+        res["stage_gb_s"][k] = {nm: round(nb[nm] / (t * 1e-3) / 1e9, 1) for nm, t in st.items()}
+        res["hbm_frac"][k] = {nm: round(nb[nm] / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 3) for nm, t in st.items()}
+        del ws, out
+        torch.cuda.empty_cache()
+    res["ratio_lo_full"] = round(res["ms"]["lo"] / res["ms"]["full"], 4)
+    res["ratio_hi_full"] = round(res["ms"]["hi"] / res["ms"]["full"], 4)
+    res["mbit_s"] = {k: round(n / (res["ms"][k] * 1e-3) / 1e6, 1) for k in res["ms"]}
+    return res
+
+
 def serving_bench(count=4096, n_streams=4):
     """Mixed-request serving through the continuous-batching server: count
     requests, n log-uniform over [2^12, 2^22] bits (whole limbs), kind
@@ -155,6 +206,8 @@ def main():
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the mixed-request serving runs")
+    ap.add_argument("--large-log2n", type=int, default=30,
+                    help="also time the three products at n = 2^this (0: skip)")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="run the counter-collection workload instead of the benchmark")
     args = ap.parse_args()
@@ -284,6 +337,10 @@ def main():
         "source_hash": source_hash(),
         "wall_s_timed": round(wall, 3),
     }
+    del ws, outs
+    torch.cuda.empty_cache()
+    if args.large_log2n:
+        result["large_n"] = large_n_bench(args.large_log2n, 5)
     if not args.no_serve:
         result["serving"] = serving_bench()
     if not args.no_cpu:

@@ -95,7 +95,9 @@ typedef struct {
     uint32_t L1, L2;        /* M = L1 * Lm * L2: column and row sub-transform     */
     uint64_t workspace_bytes;
     uint32_t Lm;            /* middle sub-transform length (1: two-pass FFT)      */
-    uint32_t reserved;
+    uint32_t guaranteed;    /* 1 if rounding_bound <= 0.45 (see tm_mul_guaranteed) */
+    double rounding_bound;  /* worst-case bound on |x - exact| over the rounded
+                               values x of this plan (tm_mul_guaranteed)         */
 } tm_plan_info;
 
 /* One request of a batch: w = product(kind, u, v) on n_bits-bit operands. */
@@ -155,12 +157,31 @@ tm_status tm_mul_batched(const tm_request* reqs, size_t count, void* workspace,
 
 /*
  * Like tm_mul, then synchronises the stream and reads the guard.  If it
- * tripped, recomputes with the fallback plan (smaller digits, see
- * tm_workspace_bytes_checked) and checks again.  *guard_host (may be NULL)
+ * tripped, recomputes with the fallback plan (the guaranteed plan when one
+ * exists, else two bits smaller digits for the truncated products and four
+ * for the full product; see tm_workspace_bytes_checked) and checks again.  *guard_host (may be NULL)
  * receives the guard of the last run.  Returns TM_ERR_PRECISION if the
  * fallback tripped too.
  */
 size_t tm_workspace_bytes_checked(tm_kind kind, uint64_t n_bits);
+
+/*
+ * Guaranteed mode: the same products with the digit size taken from a
+ * worst-case rounding-error bound instead of the statistical default
+ * (Section 5 chooses its parameters by testing).  With balanced digits
+ * |U_i| <= 2^(b-1) and map gains 1 + 4 2^-b, the FFT convolution error is at
+ * most ||G_u||_2 ||G_v||_2 ((1+u)^(3k) (1+sqrt5 u)^(3k+1) (1+t)^(3k) - 1),
+ * u = 2^-53, t = 2^-49, k = ceil(lg M) + 4; scaled by 2^b for the truncated
+ * products, plus 2^-8 of series truncation, it must stay below 0.45.  The
+ * largest such b (at most the default) is used: every rounded coefficient is
+ * then provably the nearest integer, for every input.  TM_ERR_UNSUPPORTED if
+ * no b >= 8 qualifies (truncated products beyond about 2^22 bits).
+ */
+size_t tm_workspace_bytes_guaranteed(tm_kind kind, uint64_t n_bits);
+tm_status tm_plan_query_guaranteed(tm_kind kind, uint64_t n_bits, tm_plan_info* out);
+tm_status tm_mul_guaranteed(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v,
+                            uint64_t n_bits, void* workspace, size_t workspace_bytes,
+                            hipStream_t stream, tm_guard* guard_dev);
 tm_status tm_mul_checked(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v,
                          uint64_t n_bits, void* workspace, size_t workspace_bytes,
                          hipStream_t stream, tm_guard* guard_host);

@@ -47,7 +47,7 @@ class _PlanInfo(ctypes.Structure):
                 ("digits", ctypes.c_uint64), ("M", ctypes.c_uint64),
                 ("L1", ctypes.c_uint32), ("L2", ctypes.c_uint32),
                 ("workspace_bytes", ctypes.c_uint64), ("Lm", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("guaranteed", ctypes.c_uint32), ("rounding_bound", ctypes.c_double)]
 
 
 class _Request(ctypes.Structure):
@@ -72,6 +72,12 @@ def _load():
     lib.tm_workspace_bytes_batched.argtypes = [P, SZ]
     lib.tm_workspace_bytes_batched.restype = SZ
     lib.tm_plan_query.argtypes = [I32, U64, ctypes.POINTER(_PlanInfo)]
+    lib.tm_plan_query_guaranteed.argtypes = [I32, U64, ctypes.POINTER(_PlanInfo)]
+    lib.tm_plan_query_guaranteed.restype = I32
+    lib.tm_workspace_bytes_guaranteed.argtypes = [I32, U64]
+    lib.tm_workspace_bytes_guaranteed.restype = SZ
+    lib.tm_mul_guaranteed.argtypes = [I32, P, P, P, U64, P, SZ, P, P]
+    lib.tm_mul_guaranteed.restype = I32
     lib.tm_mul.argtypes = [I32, P, P, P, U64, P, SZ, P, P]
     for name in ("tm_mul_full", "tm_mul_lo", "tm_mul_hi"):
         getattr(lib, name).argtypes = [P, P, P, U64, P, SZ, P, P]
@@ -133,10 +139,13 @@ def nlimbs(n_bits):
     return (int(n_bits) + 63) // 64
 
 
-def plan(kind, n_bits):
-    """The plan (b, lambda, N, FFT split, workspace) used for (kind, n_bits)."""
+def plan(kind, n_bits, guaranteed=False):
+    """The plan (b, lambda, N, FFT split, workspace, rounding bound) used for
+    (kind, n_bits); guaranteed=True: the plan of tm_mul_guaranteed."""
     info = _PlanInfo()
-    _check(_load().tm_plan_query(_kind(kind), int(n_bits), ctypes.byref(info)), "plan")
+    lib = _load()
+    f = lib.tm_plan_query_guaranteed if guaranteed else lib.tm_plan_query
+    _check(f(_kind(kind), int(n_bits), ctypes.byref(info)), "plan")
     return {k: getattr(info, k) for k, _ in _PlanInfo._fields_}
 
 
@@ -183,12 +192,15 @@ def read_guard(buf):
     return Guard.from_buffer_copy(raw[:ctypes.sizeof(Guard)])
 
 
-def mul(kind, u, v, n_bits, out=None, workspace=None, stream=None, guard=None):
+def mul(kind, u, v, n_bits, out=None, workspace=None, stream=None, guard=None,
+        guaranteed=False):
     """w = product of ``kind`` ('lo', 'hi' or 'full') of u and v (n_bits each).
 
     Returns the output tensor (L limbs for lo/hi, 2L for full), enqueued on
     ``stream`` (default: torch's current stream).  ``guard`` may be a tensor
-    from new_guard() to receive the rounding guard."""
+    from new_guard() to receive the rounding guard.  ``guaranteed``: use the
+    digit size of the worst-case rounding bound (tm_mul_guaranteed).  Passing
+    the same tensor as u and v computes a square with one forward transform."""
     k = _kind(kind)
     L = nlimbs(n_bits)
     dev = u.device
@@ -197,11 +209,18 @@ def mul(kind, u, v, n_bits, out=None, workspace=None, stream=None, guard=None):
     if out is None:
         out = torch.empty(nout, dtype=torch.uint64, device=dev)
     pw = _dev_ptr(out, nout, "out")
-    nb = workspace_bytes(k, n_bits)
+    lib = _load()
+    if guaranteed:
+        nb = lib.tm_workspace_bytes_guaranteed(k, int(n_bits))
+        if nb == 0:
+            raise TmulError("no guaranteed plan for (%s, %d)" % (kind, n_bits))
+    else:
+        nb = workspace_bytes(k, n_bits)
     ws = _workspace(nb, dev, workspace)
     g = ctypes.c_void_p(guard.data_ptr()) if guard is not None else None
-    _check(_load().tm_mul(k, pw, pu, pv, int(n_bits), ctypes.c_void_p(ws.data_ptr()),
-                          ws.numel() * ws.element_size(), _stream_ptr(stream, dev), g), "tm_mul")
+    f = lib.tm_mul_guaranteed if guaranteed else lib.tm_mul
+    _check(f(k, pw, pu, pv, int(n_bits), ctypes.c_void_p(ws.data_ptr()),
+             ws.numel() * ws.element_size(), _stream_ptr(stream, dev), g), "tm_mul")
     return out
 
 

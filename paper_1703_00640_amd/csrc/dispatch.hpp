@@ -1,0 +1,60 @@
+// Template dispatch shared by the host translation units: column tile
+// widths, the list of column lengths L1 with kernel instances, the choice of
+// compile-time digit size, and the K1 launchers (one translation unit per
+// kind, so the instances compile in parallel).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace tmul {
+
+// column tile width: the largest power of two W <= 8 with L1 W <= tile
+constexpr int w_for(int L1, int tile)
+{
+    int lim = tile / L1 < 8 ? tile / L1 : 8;
+    int w = 1;
+    while (w * 2 <= lim) w *= 2;
+    return w;
+}
+constexpr int w1_for(int L1) { return w_for(L1, TILE1); }
+constexpr int w3_for(int L1) { return w_for(L1, TILE3); }
+
+#define TM_L1_LIST(X) \
+    X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) \
+    X(256) X(384) X(512) X(768) X(1024) X(5) X(10) X(20) X(40) X(80) X(160) X(320) X(640)
+
+// Compile-time digit size of the K1 / K4 instances for a plan: the default
+// sizes (b = 11 truncated with lam <= LB_FIXED, b = 16 full) have their own
+// instances; every other plan runs the generic ones (B = 0).
+inline int fixed_b(int kind, const KParams& p)
+{
+    if (kind == TM_FULL) return p.b == B_FULL ? B_FULL : 0;
+    return p.b == B_TRUNC && p.lam <= LB_FIXED ? B_TRUNC : 0;
+}
+
+template <int KIND, int B>
+bool launch_k1_b(uint32_t L1, const KParams& p, hipStream_t s)
+{
+    switch (L1) {
+#define X(V) \
+    case V: hipLaunchKernelGGL((k1_split_map_col<V, w1_for(V), KIND, B>), dim3(p.R / w1_for(V), p.zb == p.za ? 1 : 2), dim3(NT1), 0, s, p); return true;
+        TM_L1_LIST(X)
+#undef X
+    }
+    return false;
+}
+
+template <int KIND, int BF>
+bool launch_k1(uint32_t L1, const KParams& p, hipStream_t s)
+{
+    return fixed_b(KIND, p) ? launch_k1_b<KIND, BF>(L1, p, s) : launch_k1_b<KIND, 0>(L1, p, s);
+}
+
+// defined in k1_full.hip, k1_lo.hip, k1_hi.hip
+bool launch_k1_full(uint32_t L1, const KParams& p, hipStream_t s);
+bool launch_k1_lo(uint32_t L1, const KParams& p, hipStream_t s);
+bool launch_k1_hi(uint32_t L1, const KParams& p, hipStream_t s);
+
+}  // namespace tmul

@@ -2,7 +2,7 @@
 //
 // This is the building block of the Convolution step (Section 2.1: real
 // FFTs, pointwise product, inverse FFT).  A tile holds NB independent
-// sequences of length P; a Stockham autosort schedule of radix-3/16/8/4/2
+// sequences of length P; a Stockham autosort schedule of radix-3/5/16/8/4/2
 // stages transforms all of them in place, one LDS round trip per stage
 // (radix 16 runs as 4 x 4 in registers).  Each butterfly reads one stage
 // twiddle from an LDS copy of exp(-2 pi i e / P) and forms the others as
@@ -90,6 +90,27 @@ __device__ __forceinline__ void dft3(double2* v)
     v[0] = cadd(v[0], s);
     v[1] = cadd(t, u);
     v[2] = csub(t, u);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft5(double2* v)
+{
+    const double c1 = 0.30901699437494742410;   // cos(2 pi / 5)
+    const double c2 = -0.80901699437494742410;  // cos(4 pi / 5)
+    const double s1 = 0.95105651629515357212;   // sin(2 pi / 5)
+    const double s2 = 0.58778525229247312917;   // sin(4 pi / 5)
+    const double2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    const double2 t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+    const double2 a1 = make_double2(fma(c2, t2.x, fma(c1, t1.x, v[0].x)), fma(c2, t2.y, fma(c1, t1.y, v[0].y)));
+    const double2 a2 = make_double2(fma(c1, t2.x, fma(c2, t1.x, v[0].x)), fma(c1, t2.y, fma(c2, t1.y, v[0].y)));
+    // -i (forward) or +i (inverse) times b1 = s1 t3 + s2 t4, b2 = s2 t3 - s1 t4
+    const double2 b1 = mul_mi<INV>(make_double2(fma(s2, t4.x, s1 * t3.x), fma(s2, t4.y, s1 * t3.y)));
+    const double2 b2 = mul_mi<INV>(make_double2(fma(-s1, t4.x, s2 * t3.x), fma(-s1, t4.y, s2 * t3.y)));
+    v[0] = cadd(v[0], cadd(t1, t2));
+    v[1] = cadd(a1, b1);
+    v[4] = csub(a1, b1);
+    v[2] = cadd(a2, b2);
+    v[3] = csub(a2, b2);
 }
 
 template <bool INV>
@@ -185,6 +206,7 @@ __device__ __forceinline__ void dftR(double2* v)
     if constexpr (R == 2) dft2<INV>(v);
     else if constexpr (R == 3) dft3<INV>(v);
     else if constexpr (R == 4) dft4<INV>(v);
+    else if constexpr (R == 5) dft5<INV>(v);
     else if constexpr (R == 8) dft8<INV>(v);
     else dft16<INV>(v);
 }
@@ -202,7 +224,7 @@ __device__ __forceinline__ void tw_powers(double2 w, double2* pw)
 // radix of the next stage given the remaining length
 constexpr int pick_radix(int rem)
 {
-    return rem % 3 == 0 ? 3 : rem % 16 == 0 ? 16 : rem % 8 == 0 ? 8 : rem % 4 == 0 ? 4 : 2;
+    return rem % 3 == 0 ? 3 : rem % 5 == 0 ? 5 : rem % 16 == 0 ? 16 : rem % 8 == 0 ? 8 : rem % 4 == 0 ? 4 : 2;
 }
 
 // LDS tiles are padded by one element after every 16, which spreads the

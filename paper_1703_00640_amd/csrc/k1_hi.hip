@@ -1,0 +1,11 @@
+// K1 instances (split + map + column FFT) of the high product.
+#include "dispatch.hpp"
+
+namespace tmul {
+
+bool launch_k1_hi(uint32_t L1, const KParams& p, hipStream_t s)
+{
+    return launch_k1<K_HI, B_TRUNC>(L1, p, s);
+}
+
+}  // namespace tmul

@@ -26,9 +26,8 @@ namespace tmul {
 
 enum { K_FULL = 0, K_LO = 1, K_HI = 2 };
 
-constexpr int NT = 256;         // threads per workgroup, every kernel
+constexpr int NT = 256;         // threads per workgroup (K2 and the middle pass)
 constexpr int LMAX = 9;         // largest supported series length lambda
-constexpr int DPT = TM_DPT;     // coefficients per thread in K4
 #ifndef TM_NT4
 #define TM_NT4 512
 #endif
@@ -38,6 +37,7 @@ constexpr int DPT = TM_DPT;     // coefficients per thread in K4
 #ifndef TM_DPT
 #define TM_DPT 8
 #endif
+constexpr int DPT = TM_DPT;     // coefficients per thread in K4
 constexpr int NT4 = TM_NT4;     // threads per K4 workgroup
 constexpr int NT3 = TM_NT3;     // threads per K3 workgroup
 constexpr int DPW = DPT * NT4;  // coefficients per workgroup in K4
@@ -1016,9 +1016,7 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
         }
     }
     if (KIND != K_FULL && i0 == 0 && (c[0] & ((1ll << b) - 1)) != 0) gflags |= TM_GUARD_C0;
-    // guard: reduce over the workgroup, then one atomic per field and only
-    // when it raises the stored maximum (non-negative doubles order like
-    // their bit patterns)
+    // guard: reduce over the workgroup (published at the end)
     dmax = wave_max(dmax);
     amax = wave_max(amax);
     if (gflags) atomicOr(&sGF, gflags);
@@ -1027,22 +1025,29 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
         sGA[wv] = amax;
     }
     __syncthreads();
-    if (tid == 0) {
+    // guard: one atomic per field and only when it raises the stored
+    // maximum (non-negative doubles order like their bit patterns).  Done by
+    // the last wave after its share of the work, off the other waves' path.
+    auto publish_guard = [&]() {
+        double dm = sGD[0], am = sGA[0];
         for (int w2 = 1; w2 < NW; w2++) {
-            dmax = fmax(dmax, sGD[w2]);
-            amax = fmax(amax, sGA[w2]);
+            dm = fmax(dm, sGD[w2]);
+            am = fmax(am, sGA[w2]);
         }
         uint64_t* gd = reinterpret_cast<uint64_t*>(&p.guard->max_dist);
         uint64_t* ga = reinterpret_cast<uint64_t*>(&p.guard->max_abs);
-        const uint64_t bd = (uint64_t)__double_as_longlong(dmax);
-        const uint64_t ba = (uint64_t)__double_as_longlong(amax);
+        const uint64_t bd = (uint64_t)__double_as_longlong(dm);
+        const uint64_t ba = (uint64_t)__double_as_longlong(am);
         if (bd > ld_rlx(gd)) atomicMax(reinterpret_cast<unsigned long long*>(gd), (unsigned long long)bd);
         if (ba > ld_rlx(ga)) atomicMax(reinterpret_cast<unsigned long long*>(ga), (unsigned long long)ba);
-        const uint32_t f = sGF | (dmax >= 0.25 ? TM_GUARD_DIST : 0u) |
-                           (amax >= 1125899906842624.0 ? TM_GUARD_ABS : 0u);
+        const uint32_t f = sGF | (dm >= 0.25 ? TM_GUARD_DIST : 0u) |
+                           (am >= 1125899906842624.0 ? TM_GUARD_ABS : 0u);
         if (f) atomicOr(&p.guard->flags, f);
+    };
+    if (DIAG) {
+        if (tid == 0) publish_guard();
+        return;
     }
-    if (DIAG) return;
 
     if (KIND == K_HI) {
         // round(t) = floor((S + 2^(D-1)) / 2^D): add 2^(D-1) at its digit
@@ -1224,7 +1229,7 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
     const int64_t ob0 = sb0 - (int64_t)p.off, ob1 = sb1 - (int64_t)p.off;
     const int64_t lo_o = ob0 > 0 ? ob0 : 0;
     const int64_t hi_o = ob1 < (int64_t)p.out_bits ? ob1 : (int64_t)p.out_bits;
-    if (hi_o <= lo_o) return;
+    if (hi_o > lo_o) {
     const int64_t l0 = lo_o >> 6, l1 = (hi_o - 1) >> 6;
     const int r = (int)(p.off & 63);
     for (int64_t li = l0 + tid; li <= l1; li += NT4) {
@@ -1241,35 +1246,8 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
         if (full) p.w[li] = val;
         else atomicOr(reinterpret_cast<unsigned long long*>(&p.w[li]), (unsigned long long)val);
     }
-}
-
-// sub-transform table: t[e] = exp(-2 pi i e / P), e < P
-__global__ void k_subtwiddles(double2* t, uint32_t P)
-{
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < P) {
-        const int64_t ee = i > P / 2 ? (int64_t)i - (int64_t)P : (int64_t)i;
-        double s, c;
-        sincospi(-2.0 * ((double)ee / (double)P), &s, &c);
-        t[i] = make_double2(c, s);
     }
-}
-
-// twiddle table: lo[e] = exp(-2 pi i e/M) for e < S, hi[e] = exp(-2 pi i e S/M)
-__global__ void k_twiddles(double2* lo, double2* hi, uint32_t M, uint32_t S, uint32_t nhi)
-{
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < S) {
-        double s, c;
-        sincospi(-2.0 * ((double)i / (double)M), &s, &c);
-        lo[i] = make_double2(c, s);
-    }
-    if (i < nhi) {
-        const uint64_t e = ((uint64_t)i * S) % M;
-        double s, c;
-        sincospi(-2.0 * ((double)e / (double)M), &s, &c);
-        hi[i] = make_double2(c, s);
-    }
+    if (tid == NT4 - 64) publish_guard();
 }
 
 }  // namespace tmul

@@ -5,9 +5,10 @@
 //   full: N_digits b >= n, convolution length 2 N_digits;
 //   low:  b >= 4, N >= 3, N b >= n;
 //   high: b >= 4, N >= 3, (N + 1) b >= n + lg N + 2.
-// Lengths are restricted to {2^a, 3 * 2^a} (smooth lengths, Section 2.2)
-// and split as M = N/2 = L1 * L2 for the two-pass FFT.
+// Lengths are restricted to {2^a, 3 * 2^a, 5 * 2^a} (smooth lengths,
+// Section 2.2) and split as M = N/2 = L1 * Lm * L2.
 #pragma once
+#include <math.h>
 #include <stdint.h>
 #include <stddef.h>
 
@@ -55,18 +56,17 @@ inline int lg_ceil(uint64_t x)
 inline bool l1_supported(uint64_t x)
 {
     if (x < 2 || x > L1_MAX) return false;
-    uint64_t y = x % 3 == 0 ? x / 3 : x;
+    uint64_t y = x % 3 == 0 ? x / 3 : x % 5 == 0 ? x / 5 : x;
     return (y & (y - 1)) == 0;
 }
 
-// M = L1 * L2 with L2 a power of two in [16, 1024] near sqrt(M)
 inline bool split_M(uint64_t M, uint32_t& L1, uint32_t& L2)
 {
     if (M < 32) return false;
     int a = 0;
     while (((M >> a) & 1) == 0) a++;
     uint64_t odd = M >> a;
-    if (odd != 1 && odd != 3) return false;
+    if (odd != 1 && odd != 3 && odd != 5) return false;
     int lg = (lg_ceil(M) + 1) / 2;
     if (lg < 4) lg = 4;
     if (lg > 10) lg = 10;
@@ -95,15 +95,17 @@ inline bool split_M3(uint64_t M, uint32_t force_lm, uint32_t& L1, uint32_t& Lm, 
     return false;
 }
 
-// smallest N in {2^a, 3*2^a}, N >= max(x, 64)
+// smallest N in {2^a, 3*2^a, 5*2^(a>=5)}, N >= max(x, 64)
 inline uint64_t next_smooth(uint64_t x)
 {
     if (x < 64) x = 64;
     uint64_t best = UINT64_MAX;
     for (int a = 0; a < 62; a++) {
-        uint64_t p2 = 1ull << a;
+        const uint64_t p2 = 1ull << a;
         if (p2 >= x && p2 < best) best = p2;
         if (a < 60 && 3 * p2 >= x && 3 * p2 < best) best = 3 * p2;
+        // 5 * 2^a from a = 5 on, so that M = N/2 keeps a row length of 16
+        if (a >= 5 && a < 59 && 5 * p2 >= x && 5 * p2 < best) best = 5 * p2;
     }
     return best;
 }
@@ -179,6 +181,63 @@ inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P, ui
     P.o_theta = o; o = align256(o + 2 * sizeof(double));
     P.ws_bytes = o;
     return true;
+}
+
+// ------------------------------------------------------- guaranteed mode
+//
+// The default digit sizes are chosen statistically (Section 5 picks its
+// parameters by testing; the rounding guard catches the rest).  Guaranteed
+// mode instead takes the largest b whose worst-case rounding error bound
+// stays below 0.45:
+//   * digits |U_i| <= 2^(b-1) (the top digit <= 2^b), map outputs
+//     |G_j| <= g 2^(b-1) with g = 1 + 4 2^-b (the series coefficients are
+//     bounded by 2^-rb, Sections 3.2 and 4.2, and the wrap and recovery terms
+//     add factors 1 + O(2^-b));
+//   * the FFT convolution differs from the exact one by at most
+//     ||G_u||_2 ||G_v||_2 eta, eta = (1+u)^(3k) (1+sqrt5 u)^(3k+1) (1+t)^(3k) - 1
+//     (the standard error bound of FFT-based convolution of length 2^k, unit
+//     roundoff u = 2^-53, twiddle error t), taken with k = ceil(lg M) + 4 to
+//     cover the radix-3/16 codelets, the packed real transform, the
+//     inter-pass twiddles and the 1/M scaling, and t = 2^-49;
+//   * the truncated products scale by 2^b and the back map's gain g, and the
+//     series truncation adds at most 2^-8 (the choice of lambda).
+inline double conv_eta(uint64_t M)
+{
+    const double u = ldexp(1.0, -53), t = ldexp(1.0, -49);
+    const double k = (double)(lg_ceil(M) + 4);
+    return expm1(3 * k * log1p(u) + (3 * k + 1) * log1p(sqrt(5.0) * u) + 3 * k * log1p(t));
+}
+
+// Bound on |x - exact| over all rounded values x of plan P (see above).
+inline double rounding_bound(const Plan& P)
+{
+    const double eta = conv_eta(P.M);
+    if (P.kind == TM_FULL) {
+        const double nrm2 = (double)(P.digits - 1) * ldexp(1.0, 2 * P.b - 2) + ldexp(1.0, 2 * P.b);
+        return nrm2 * eta;
+    }
+    const double g = 1.0 + 4.0 * ldexp(1.0, -P.b);
+    const double nrm2 = g * g * ((double)(P.N - 1) * ldexp(1.0, 2 * P.b - 2) + ldexp(1.0, 2 * P.b));
+    return ldexp(g * nrm2 * eta, P.b) + ldexp(1.0, -8);
+}
+
+constexpr double GUARANTEED_MAX = 0.45;
+
+// The guaranteed plan: the largest b (at most the default) whose bound is
+// below GUARANTEED_MAX; false if none with b >= 8 exists.
+inline bool make_plan_guaranteed(int kind, uint64_t n, Plan& P)
+{
+    for (int b = B_FULL; b >= 8; b--) {
+        Plan Q;
+        const int bt = b <= 15 ? b : 0;  // truncated digit sizes stop at 15
+        if (kind != TM_FULL && b > B_TRUNC && n >= TRUNC_MIN_BITS) continue;
+        if (!make_plan(kind, n, bt, b, Q)) continue;
+        if (rounding_bound(Q) <= GUARANTEED_MAX) {
+            P = Q;
+            return true;
+        }
+    }
+    return false;
 }
 
 }  // namespace tmul

@@ -13,6 +13,7 @@
 #include "tmul.h"
 #include "plan.hpp"
 #include "kernels.hpp"
+#include "dispatch.hpp"
 
 using namespace tmul;
 
@@ -37,6 +38,44 @@ tm_status hip_fail(hipError_t e, const char* what)
     } while (0)
 
 // ------------------------------------------------------------ twiddles
+
+}  // namespace
+
+namespace tmul {
+
+// sub-transform table: t[e] = exp(-2 pi i e / P), e < P
+__global__ void k_subtwiddles(double2* t, uint32_t P)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P) {
+        const int64_t ee = i > P / 2 ? (int64_t)i - (int64_t)P : (int64_t)i;
+        double s, c;
+        sincospi(-2.0 * ((double)ee / (double)P), &s, &c);
+        t[i] = make_double2(c, s);
+    }
+}
+
+// twiddle table: lo[e] = exp(-2 pi i e/M) for e < S, hi[e] = exp(-2 pi i e S/M)
+__global__ void k_twiddles(double2* lo, double2* hi, uint32_t M, uint32_t S, uint32_t nhi)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < S) {
+        double s, c;
+        sincospi(-2.0 * ((double)i / (double)M), &s, &c);
+        lo[i] = make_double2(c, s);
+    }
+    if (i < nhi) {
+        const uint64_t e = ((uint64_t)i * S) % M;
+        double s, c;
+        sincospi(-2.0 * ((double)e / (double)M), &s, &c);
+        hi[i] = make_double2(c, s);
+    }
+}
+
+}  // namespace tmul
+
+namespace {
+
 
 struct TwEntry {
     double2* buf = nullptr;
@@ -88,48 +127,6 @@ tm_status get_twiddles(uint64_t M, uint32_t L1, uint32_t Lm, uint32_t L2, hipStr
 }
 
 // ------------------------------------------------------------ dispatch
-
-// column tile width: the largest power of two W <= 8 with L1 W <= tile
-constexpr int w_for(int L1, int tile)
-{
-    int lim = tile / L1 < 8 ? tile / L1 : 8;
-    int w = 1;
-    while (w * 2 <= lim) w *= 2;
-    return w;
-}
-constexpr int w1_for(int L1) { return w_for(L1, TILE1); }
-constexpr int w3_for(int L1) { return w_for(L1, TILE3); }
-
-#define TM_L1_LIST(X) \
-    X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) \
-    X(256) X(384) X(512) X(768) X(1024)
-
-// Compile-time digit size of the K1 / K4 instances for a plan: the default
-// sizes (b = 11 truncated with lam <= LB_FIXED, b = 16 full) have their own
-// instances; every other plan runs the generic ones (B = 0).
-int fixed_b(int kind, const KParams& p)
-{
-    if (kind == TM_FULL) return p.b == B_FULL ? B_FULL : 0;
-    return p.b == B_TRUNC && p.lam <= LB_FIXED ? B_TRUNC : 0;
-}
-
-template <int KIND, int B>
-bool launch_k1_b(uint32_t L1, const KParams& p, hipStream_t s)
-{
-    switch (L1) {
-#define X(V) \
-    case V: hipLaunchKernelGGL((k1_split_map_col<V, w1_for(V), KIND, B>), dim3(p.R / w1_for(V), p.zb == p.za ? 1 : 2), dim3(NT1), 0, s, p); return true;
-        TM_L1_LIST(X)
-#undef X
-    }
-    return false;
-}
-
-template <int KIND, int BF>
-bool launch_k1(uint32_t L1, const KParams& p, hipStream_t s)
-{
-    return fixed_b(KIND, p) ? launch_k1_b<KIND, BF>(L1, p, s) : launch_k1_b<KIND, 0>(L1, p, s);
-}
 
 bool launch_k3(uint32_t L1, const KParams& p, hipStream_t s)
 {
@@ -191,9 +188,9 @@ void launch_k4(int kind, const KParams& p, hipStream_t s)
 
 bool launch_k1_any(int kind, const KParams& p, hipStream_t s)
 {
-    if (kind == TM_FULL) return launch_k1<K_FULL, B_FULL>(p.L1, p, s);
-    if (kind == TM_LO) return launch_k1<K_LO, B_TRUNC>(p.L1, p, s);
-    return launch_k1<K_HI, B_TRUNC>(p.L1, p, s);
+    if (kind == TM_FULL) return launch_k1_full(p.L1, p, s);
+    if (kind == TM_LO) return launch_k1_lo(p.L1, p, s);
+    return launch_k1_hi(p.L1, p, s);
 }
 
 // ------------------------------------------------------------ params
@@ -371,13 +368,46 @@ tm_status run(const Plan& P, uint64_t* w, const uint64_t* u, const uint64_t* v, 
     return TM_OK;
 }
 
-// Fallback plan of tm_mul_checked: two bits smaller digits for the truncated
-// products, four bits smaller for the full product.
+// Fallback plan of tm_mul_checked: the guaranteed plan if there is one with
+// smaller digits, else two bits smaller digits for the truncated products
+// and four bits smaller for the full product.
 bool fallback_plan(tm_kind kind, uint64_t n_bits, const Plan& P, Plan& F)
 {
+    if (make_plan_guaranteed((int)kind, n_bits, F) && F.b < P.b) return true;
     int bt = P.kind == TM_FULL ? 0 : P.b - 2;
     int bf = P.kind == TM_FULL ? P.b - 4 : 0;
     return make_plan((int)kind, n_bits, bt, bf, F);
+}
+
+tm_status plan_guaranteed(tm_kind kind, uint64_t n, Plan& P)
+{
+    if ((int)kind < 0 || (int)kind > 2 || n == 0) {
+        g_last_error = "invalid kind or size";
+        return TM_ERR_INVALID;
+    }
+    if (!make_plan_guaranteed((int)kind, n, P)) {
+        g_last_error = "no digit size >= 8 meets the guaranteed bound at this size";
+        return TM_ERR_UNSUPPORTED;
+    }
+    return TM_OK;
+}
+
+void fill_info(tm_kind kind, uint64_t n_bits, const Plan& P, tm_plan_info* out)
+{
+    out->kind = (uint32_t)kind;
+    out->via_full = P.via_full ? 1u : 0u;
+    out->b = (uint32_t)P.b;
+    out->lambda = (uint32_t)P.lam;
+    out->n_bits = n_bits;
+    out->N = P.N;
+    out->digits = P.digits;
+    out->M = P.M;
+    out->L1 = P.L1;
+    out->L2 = P.L2;
+    out->workspace_bytes = P.ws_bytes;
+    out->Lm = P.Lm;
+    out->rounding_bound = rounding_bound(P);
+    out->guaranteed = out->rounding_bound <= GUARANTEED_MAX ? 1u : 0u;
 }
 
 }  // namespace
@@ -402,20 +432,38 @@ tm_status tm_plan_query(tm_kind kind, uint64_t n_bits, tm_plan_info* out)
     Plan P;
     tm_status st = plan_for(kind, n_bits, P);
     if (st != TM_OK) return st;
-    out->kind = (uint32_t)kind;
-    out->via_full = P.via_full ? 1u : 0u;
-    out->b = (uint32_t)P.b;
-    out->lambda = (uint32_t)P.lam;
-    out->n_bits = n_bits;
-    out->N = P.N;
-    out->digits = P.digits;
-    out->M = P.M;
-    out->L1 = P.L1;
-    out->L2 = P.L2;
-    out->workspace_bytes = P.ws_bytes;
-    out->Lm = P.Lm;
-    out->reserved = 0;
+    fill_info(kind, n_bits, P, out);
     return TM_OK;
+}
+
+size_t tm_workspace_bytes_guaranteed(tm_kind kind, uint64_t n_bits)
+{
+    Plan P;
+    return plan_guaranteed(kind, n_bits, P) == TM_OK ? P.ws_bytes : 0;
+}
+
+tm_status tm_plan_query_guaranteed(tm_kind kind, uint64_t n_bits, tm_plan_info* out)
+{
+    if (!out) {
+        g_last_error = "null pointer";
+        return TM_ERR_INVALID;
+    }
+    Plan P;
+    tm_status st = plan_guaranteed(kind, n_bits, P);
+    if (st != TM_OK) return st;
+    fill_info(kind, n_bits, P, out);
+    return TM_OK;
+}
+
+tm_status tm_mul_guaranteed(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v,
+                            uint64_t n_bits, void* workspace, size_t workspace_bytes,
+                            hipStream_t stream, tm_guard* guard_dev)
+{
+    Plan P;
+    tm_status st = plan_guaranteed(kind, n_bits, P);
+    if (st != TM_OK) return st;
+    return run(P, w, u, v, workspace, workspace_bytes, stream, guard_dev, RUN, nullptr, nullptr,
+               nullptr);
 }
 
 tm_status tm_mul(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v,

@@ -187,8 +187,8 @@ def test_large_b_truncated_trips_guard_and_checked_recovers(monkeypatch):
     """Negative control for the configs' literal b = 16 on the truncated
     product: any b with 3b + lg N well above 53 fails in FP64.  Forced here
     to b = 15 (the largest truncated digit size the kernels store); the guard
-    must trip, and the checked entry point must fall back (b = 13) and
-    return the right value."""
+    must trip, and the checked entry point must fall back to the guaranteed
+    plan and return the right value."""
     tm = _tm()
     n = 1 << 16
     u, v = inputs.operand_pair(n, 3)
@@ -197,8 +197,38 @@ def test_large_b_truncated_trips_guard_and_checked_recovers(monkeypatch):
     say("  b=15 low product guard:", g.as_dict())
     assert g.b == 15 and g.flags != 0
     out, g2 = tm.mul_checked("lo", to_dev(u), to_dev(v), n)
-    assert g2.flags == 0 and g2.b == 13
+    assert g2.flags == 0 and g2.b == tm.plan("lo", n, guaranteed=True)["b"]
     assert np.array_equal(to_host(out), oracle.mul_lo(u, v, n))
+
+
+@pytest.mark.parametrize("n", [1 << 16, 100003, 1 << 20])
+def test_guaranteed_mode(n):
+    """Guaranteed mode (digit size from the worst-case rounding bound):
+    random operands and the adversarial pattern (every digit 2^(b-1) of the
+    guaranteed b) give the oracle's products, and every rounding distance the
+    guard sees stays below the stated bound."""
+    tm = _tm()
+    for kind in ("lo", "hi", "full"):
+        pl = tm.plan(kind, n, guaranteed=True)
+        assert pl["guaranteed"] == 1 and pl["rounding_bound"] <= 0.45
+        shift = pl["N"] * pl["b"] + pl["b"] - n if kind == "hi" else 0
+        cases = [inputs.operand_pair(n, 70)]
+        a = inputs.digit_pattern(n, pl["b"], 1 << (pl["b"] - 1), shift)
+        cases.append((a, a.copy()))
+        for u, v in cases:
+            say("[guaranteed] n=%d %s b=%d bound=%.3g" % (n, kind, pl["b"], pl["rounding_bound"]))
+            g = tm.new_guard(dev())
+            w = to_host(tm.mul(kind, to_dev(u), to_dev(v), n, guard=g, guaranteed=True))
+            gd = tm.read_guard(g)
+            assert gd.b == pl["b"] and gd.flags == 0
+            assert gd.max_dist <= pl["rounding_bound"]
+            if kind == "lo":
+                assert np.array_equal(w, oracle.mul_lo(u, v, n, 8))
+            elif kind == "full":
+                assert np.array_equal(w, oracle.mul_full(u, v, n, 8))
+            else:
+                q, nz = oracle.mul_hi(u, v, n, 8)
+                assert oracle.hi_accepts(w, q, nz)
 
 
 def test_batched_matches_single():
@@ -228,6 +258,19 @@ def test_forced_three_pass_split(monkeypatch, lm, n):
     say("[parity] forced Lm=%d n=%d" % (lm, n))
     u, v = inputs.operand_pair(n, 40 + lm)
     check_all(u, v, n)
+
+
+@pytest.mark.parametrize("n", [40960, 56220, 3000000])
+def test_radix5_lengths(n):
+    """Lengths 5 * 2^a (radix-5 column stages): n = 40960 gives the full
+    product 2N = 5120, n = 56220 the truncated N = 5120, n = 3e6 the high
+    product N = 327680 (L1 = 320)."""
+    tm = _tm()
+    plans = {k: tm.plan(k, n) for k in ("lo", "hi", "full")}
+    say("[parity] radix-5 n=%d" % n, {k: (p["N"], p["L1"], p["L2"]) for k, p in plans.items()})
+    assert any(p["N"] % 5 == 0 for p in plans.values())
+    u, v = inputs.operand_pair(n, 80)
+    check_all(u, v, n, threads=16)
 
 
 @pytest.mark.parametrize("n,lm", [(65536, 0), (100003, 0), (65536, 4), (1 << 22, 0)])

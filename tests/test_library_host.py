@@ -59,7 +59,20 @@ def test_plans_satisfy_theorem_constraints(n):
         odd = p["N"]
         while odd % 2 == 0:
             odd //= 2
-        assert odd in (1, 3)
+        assert odd in (1, 3, 5)
+
+
+def test_every_small_size_has_kernels():
+    """Every plan for n up to 2^17 (and a sample beyond) has a row length
+    with a K2 instance (16..1024) and a column length in the instance list."""
+    import paper_1703_00640_amd as tm
+    l1_ok = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024,
+             5, 10, 20, 40, 80, 160, 320, 640}
+    sizes = list(range(1, 4097)) + list(range(4097, 1 << 17, 97)) + [10 ** 6, 3 * 10 ** 6, 10 ** 7]
+    for n in sizes:
+        for kind in ("lo", "hi", "full"):
+            p = _plan(kind, n)
+            assert 16 <= p["L2"] <= 1024 and p["L1"] in l1_ok, (kind, n, p)
 
 
 def test_config_plans():
@@ -123,3 +136,29 @@ def test_server_host_checks():
     arr = (ctypes.c_double * 2)(1.0, 0.5)
     lat = (ctypes.c_double * 2)()
     assert lib.tm_serve_trace(reqs, arr, 2, 1 << 20, 2, 0, lat, None, None) == 1
+
+
+def test_guaranteed_plans():
+    """Guaranteed mode: the largest digit size whose worst-case rounding
+    bound is below 0.45; sizes shrink as n grows, and where no b >= 8
+    qualifies the size is refused, never silently planned."""
+    import paper_1703_00640_amd as tm
+    prev = {"lo": 99, "hi": 99, "full": 99}
+    for lg in range(12, 23):
+        n = 1 << lg
+        for kind in ("lo", "hi", "full"):
+            try:
+                g = tm.plan(kind, n, guaranteed=True)
+            except tm.TmulError:
+                assert kind == "hi" and lg >= 22
+                continue
+            assert g["guaranteed"] == 1 and 0 < g["rounding_bound"] <= 0.45
+            assert 8 <= g["b"] <= tm.plan(kind, n)["b"] and g["b"] <= prev[kind]
+            prev[kind] = g["b"]
+    with pytest.raises(tm.TmulError):
+        tm.plan("lo", 1 << 24, guaranteed=True)
+    assert tm.plan("full", 1 << 30, guaranteed=True)["b"] >= 8
+    # the statistical defaults are not covered by the worst-case bound at
+    # large n (the rounding guard covers them instead)
+    assert tm.plan("lo", 1 << 24)["guaranteed"] == 0
+    assert tm._load().tm_workspace_bytes_guaranteed(1, 1 << 24) == 0
