@@ -26,7 +26,14 @@ namespace tmul {
 
 enum { K_FULL = 0, K_LO = 1, K_HI = 2 };
 
-constexpr int NT = 256;         // threads per workgroup (K2 and the middle pass)
+#ifndef TM_NT2
+#define TM_NT2 256
+#endif
+#ifndef TM_NTM
+#define TM_NTM 256
+#endif
+constexpr int NT2 = TM_NT2;     // threads per K2 workgroup
+constexpr int NTM = TM_NTM;     // threads per middle-pass workgroup
 constexpr int LMAX = 9;         // largest supported series length lambda
 #ifndef TM_NT4
 #define TM_NT4 512
@@ -56,6 +63,9 @@ constexpr int NT1 = TM_NT1;      // threads per K1 workgroup
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 constexpr int K4_HALO = 32;        // q values staged below a K4 workgroup's range
 constexpr int64_t K4_CMAX = 1ll << 57;  // bound on the carries between limbs
+// K4 staging index with one pad double after every 8: the per-thread runs
+// of 8 coefficients then start 9 doubles apart, on different LDS banks
+__host__ __device__ constexpr int padq(int e) { return e + (e >> 3); }
 
 struct KParams {
     const uint64_t* u;
@@ -586,7 +596,7 @@ __device__ __forceinline__ void k2_rows_of(uint32_t g, uint32_t L1, uint32_t Lm,
 }
 
 template <int L2>
-__global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
+__global__ __launch_bounds__(NT2) void k2_rows_pointwise(KParams p)
 {
     // rows 0,1: operands u,v at row (k1, km); rows 2,3: at the mirror row
     __shared__ double2 rows[padded(4 * L2)];
@@ -598,19 +608,19 @@ __global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
     const uint32_t kmm = k1 ? Lm - 1 - km : (km ? Lm - km : 0);
     const uint32_t rowa = k1 * Lm + km, rowb = k1m * Lm + kmm;
     const bool zero_row = k1 == 0 && km == 0;
-    load_twl<L2, NT>(twl, p.tw2);
+    load_twl<L2, NT2>(twl, p.tw2);
     // exp(-2 pi i k / M) for bin k = rho + L1 Lm k2 (rho = k1 + L1 km) is
     // exp(-2 pi i rho / M) times exp(-2 pi i k2 / L2): one table value per row
     const uint32_t rhoa = k1 + L1 * km, rhob = k1m + L1 * kmm;
     const double2 wr0a = p.tw.lo[rhoa & p.tw.mask], wr0b = p.tw.hi[rhoa >> p.tw.shift];
     const double2 wr1a = p.tw.lo[rhob & p.tw.mask], wr1b = p.tw.hi[rhob >> p.tw.shift];
     {
-        constexpr int PL = (4 * L2 + NT - 1) / NT;
+        constexpr int PL = (4 * L2 + NT2 - 1) / NT2;
         double2 v[PL];
 #pragma unroll
         for (int q = 0; q < PL; q++) {
-            const int e = threadIdx.x + q * NT;
-            if (4 * L2 % NT == 0 || e < 4 * L2) {
+            const int e = threadIdx.x + q * NT2;
+            if (4 * L2 % NT2 == 0 || e < 4 * L2) {
                 const int r = e / L2, j2 = e % L2;
                 const uint32_t row = r < 2 ? rowa : rowb;
                 const double2* src = (r & 1) ? p.zb : p.za;
@@ -619,19 +629,19 @@ __global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
         }
 #pragma unroll
         for (int q = 0; q < PL; q++) {
-            const int e = threadIdx.x + q * NT;
-            if (4 * L2 % NT == 0 || e < 4 * L2) rows[pidx(e)] = v[q];
+            const int e = threadIdx.x + q * NT2;
+            if (4 * L2 % NT2 == 0 || e < 4 * L2) rows[pidx(e)] = v[q];
         }
     }
     __syncthreads();
-    tile_fft<L2, 4, NT, false, false, L2>(rows, twl);
+    tile_fft<L2, 4, NT2, false, false, L2>(rows, twl);
 
-    constexpr int PER = (2 * L2 + NT - 1) / NT;
+    constexpr int PER = (2 * L2 + NT2 - 1) / NT2;
     const double2 wrow0 = cmul(wr0a, wr0b), wrow1 = cmul(wr1a, wr1b);
     double2 qv[PER];
 #pragma unroll
     for (int t = 0; t < PER; t++) {
-        const int e = threadIdx.x + t * NT;
+        const int e = threadIdx.x + t * NT2;
         if (e < 2 * L2) {
             const int pr = e / L2, k2 = e % L2;
             const int mk2 = zero_row ? (L2 - k2) % L2 : L2 - 1 - k2;
@@ -644,7 +654,7 @@ __global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < PER; t++) {
-        const int e = threadIdx.x + t * NT;
+        const int e = threadIdx.x + t * NT2;
         if (e < 2 * L2) {
             const int pr = e / L2, k2 = e % L2;
             rows[pidx((2 * pr) * L2 + k2)] = qv[t];
@@ -652,8 +662,8 @@ __global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
     }
     __syncthreads();
     // inverse row DFTs of rows 0 and 2 (row stride 2*L2)
-    tile_fft<L2, 2, NT, true, false, 2 * L2>(rows, twl);
-    for (int e = threadIdx.x; e < 2 * L2; e += NT) {
+    tile_fft<L2, 2, NT2, true, false, 2 * L2>(rows, twl);
+    for (int e = threadIdx.x; e < 2 * L2; e += NT2) {
         const int pr = e / L2, j2 = e % L2;
         if (pr == 1 && rowb == rowa) continue;
         p.za[(size_t)(pr ? rowb : rowa) * L2 + j2] = rows[pidx((2 * pr) * L2 + j2)];
@@ -668,43 +678,43 @@ __global__ __launch_bounds__(NT) void k2_rows_pointwise(KParams p)
 // on both operands.  Inverse: exp(+2 pi i j2 km / R), then inverse DFT, on
 // the product.  grid = (L2 / W, L1, operands).
 template <int LM, int W, bool INV>
-__global__ __launch_bounds__(NT) void k_mid_col(KParams p)
+__global__ __launch_bounds__(NTM) void k_mid_col(KParams p)
 {
-    constexpr int PER = (LM * W + NT - 1) / NT;
-    static_assert(NT % W == 0, "W must divide NT");
+    constexpr int PER = (LM * W + NTM - 1) / NTM;
+    static_assert(NTM % W == 0, "W must divide NTM");
     __shared__ double2 tile[padded(LM * W)];
     __shared__ double2 twl[twl_size(LM)];
     const uint32_t L2 = p.L2;
     const uint32_t c0 = xcd_tile(blockIdx.x, gridDim.x) * W;
     double2* a = (blockIdx.z ? p.zb : p.za) + (size_t)blockIdx.y * p.R;
     const int tid = threadIdx.x;
-    load_twl<LM, NT>(twl, p.twm);
+    load_twl<LM, NTM>(twl, p.twm);
     // twiddle exponents on the R-th root, as exponents of the M-th root (x L1)
     const uint32_t colt = c0 + tid % W;
     const uint32_t eb = (uint32_t)(((uint64_t)colt * (uint32_t)(tid / W) * p.L1) % p.M);
-    const uint32_t es = (uint32_t)(((uint64_t)colt * (uint32_t)(NT / W) * p.L1) % p.M);
+    const uint32_t es = (uint32_t)(((uint64_t)colt * (uint32_t)(NTM / W) * p.L1) % p.M);
     const double2 tb0 = p.tw.lo[eb & p.tw.mask], tb1 = p.tw.hi[eb >> p.tw.shift];
     const double2 ts0 = p.tw.lo[es & p.tw.mask], ts1 = p.tw.hi[es >> p.tw.shift];
     double2 v[PER];
 #pragma unroll
     for (int q = 0; q < PER; q++) {
-        const int e = tid + q * NT;
-        if (LM * W % NT == 0 || e < LM * W) v[q] = a[(size_t)(e / W) * L2 + colt];
+        const int e = tid + q * NTM;
+        if (LM * W % NTM == 0 || e < LM * W) v[q] = a[(size_t)(e / W) * L2 + colt];
     }
     TwSeq<PER> tws;
     if (INV) tws.init(cconj(cmul(tb0, tb1)), cconj(cmul(ts0, ts1)));
     else tws.init(cmul(tb0, tb1), cmul(ts0, ts1));
 #pragma unroll
     for (int q = 0; q < PER; q++) {
-        const int e = tid + q * NT;
-        if (LM * W % NT == 0 || e < LM * W) tile[pidx(e)] = INV ? cmul(v[q], tws.at(q)) : v[q];
+        const int e = tid + q * NTM;
+        if (LM * W % NTM == 0 || e < LM * W) tile[pidx(e)] = INV ? cmul(v[q], tws.at(q)) : v[q];
     }
     __syncthreads();
-    tile_fft<LM, W, NT, INV, true>(tile, twl);
+    tile_fft<LM, W, NTM, INV, true>(tile, twl);
 #pragma unroll
     for (int q = 0; q < PER; q++) {
-        const int e = tid + q * NT;
-        if (LM * W % NT == 0 || e < LM * W) {
+        const int e = tid + q * NTM;
+        if (LM * W % NTM == 0 || e < LM * W) {
             const double2 t = tile[pidx(e)];
             a[(size_t)(e / W) * L2 + colt] = INV ? t : cmul(t, tws.at(q));
         }
@@ -816,7 +826,7 @@ __device__ __forceinline__ double wave_max(double v)
 }
 
 // x_i, the value rounded to c_i (see tm_guard), from the LDS copy of q
-// (sq[o + K4_HALO] = q at index base + o, cyclically: workgroup 0 holds the
+// (sq[padq(o + K4_HALO)] = q at index base + o, cyclically: workgroup 0 holds the
 // top of q below its range):
 //   full: W_i                                       (Alg. full, step 4)
 //   low:  2^b W-bar_i, W-bar = beta* W mod A        (Prop. approximating
@@ -846,21 +856,21 @@ __device__ double edge_part(const KParams& p, const double* sq, uint32_t i, int 
     if (KIND == K_LO) {
         if (part == 0) {
             for (int r = 0; r < p.lam && r <= (int)i; r++)
-                s = fma(coef_back<KIND>(p, i - r, r), sq[o - r], s);
+                s = fma(coef_back<KIND>(p, i - r, r), sq[padq(o - r)], s);
             for (int r = (int)i + 1; r < p.lam; r++)
-                s = fma(coef_back<KIND>(p, p.N + i - r, r), sq[o - r], s);
+                s = fma(coef_back<KIND>(p, p.N + i - r, r), sq[padq(o - r)], s);
         } else if (part == 1 && i >= 1 && i < (uint32_t)p.lam) {
             for (int r = (int)i; r < p.lam; r++)
-                s = fma(coef_back<KIND>(p, p.N + i - 1 - r, r), sq[o - 1 - r], s);
+                s = fma(coef_back<KIND>(p, p.N + i - 1 - r, r), sq[padq(o - 1 - r)], s);
         }
     } else {
         if (part == K4_EP - 1) {
             for (int r = 0; r < p.lam && r <= (int)i; r++)
-                s = fma(coef_back<KIND>(p, i - r, r), sq[o - r], s);
+                s = fma(coef_back<KIND>(p, i - r, r), sq[padq(o - r)], s);
         } else if (part <= (int)i && part <= (int)p.jmax) {
             const int j = part;
             for (int r = (int)i - j + 1; r < p.lam; r++)
-                s = fma(coef_back<KIND>(p, p.N + i - j - r, r), sq[o - j - r], s);
+                s = fma(coef_back<KIND>(p, p.N + i - j - r, r), sq[padq(o - j - r)], s);
         }
     }
     return s;
@@ -904,7 +914,7 @@ __device__ __forceinline__ void back_chain(const KParams& p, const double* sq, i
     const double x0 = (double)k0 * p.invN;
 #pragma unroll
     for (int e = 0; e < NIN; e++) {
-        double tau = sq[s0 + e] * p.bscale;
+        double tau = sq[padq(s0 + e)] * p.bscale;
         const double xk = fma((double)e, p.invN, x0);
 #pragma unroll
         for (int r = 0; r < LB; r++) {
@@ -923,7 +933,7 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
     __shared__ uint32_t s_g;
     __shared__ int64_t s_cin;
     __shared__ double s_thW;
-    __shared__ double sq[DPW + K4_HALO];
+    __shared__ double sq[padq(DPW + K4_HALO) + 1];
     __shared__ int64_t sWA[NW], sWT[NW];
     __shared__ double sGD[NW], sGA[NW];
     __shared__ uint32_t sGF;
@@ -948,7 +958,7 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
     for (int e = tid; e < DPW + K4_HALO; e += NT4) {
         int64_t i = (int64_t)base - K4_HALO + e;
         if (i < 0 && KIND != K_FULL) i += p.N;  // cyclic: wrapped terms of the maps
-        sq[e] = (i >= 0 && i < (int64_t)p.N) ? q[i] : 0.0;
+        sq[padq(e)] = (i >= 0 && i < (int64_t)p.N) ? q[i] : 0.0;
     }
     __syncthreads();
 
@@ -956,7 +966,7 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
     double xv[DPT];
     if constexpr (KIND == K_FULL) {
 #pragma unroll
-        for (int t = 0; t < DPT; t++) xv[t] = sq[tid * DPT + t + K4_HALO] * p.bscale;
+        for (int t = 0; t < DPT; t++) xv[t] = sq[padq(tid * DPT + t + K4_HALO)] * p.bscale;
     } else {
         constexpr int OFF = KIND == K_HI ? 1 : 0;
         constexpr int NOUT = DPT + OFF;
@@ -1027,7 +1037,7 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
     __syncthreads();
     // guard: one atomic per field and only when it raises the stored
     // maximum (non-negative doubles order like their bit patterns).  Done by
-    // the last wave after its share of the work, off the other waves' path.
+    // wave 1 during the look-back, off the other waves' path.
     auto publish_guard = [&]() {
         double dm = sGD[0], am = sGA[0];
         for (int w2 = 1; w2 < NW; w2++) {
@@ -1063,7 +1073,7 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
     int64_t* sc = reinterpret_cast<int64_t*>(sq);  // coefficients reuse the q staging area
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < DPT; t++) sc[tid * DPT + t] = c[t];
+    for (int t = 0; t < DPT; t++) sc[padq(tid * DPT + t)] = c[t];
     __syncthreads();
     const int LPW = DPW / 64 * b;
     // limbs per thread: lpt or lpt + 1 (threads below ex), at most MLPT
@@ -1087,7 +1097,7 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
             for (int u = 0; u < (64 + 7) / 8 + 1; u++) {
                 const int i = ia + u;
                 if (i < ib) {
-                    const int64_t cv = sc[i];
+                    const int64_t cv = sc[padq(i)];
                     const int sh = i * b - 64 * j;
                     const uint64_t plo = (uint64_t)cv << sh;
                     const int64_t phi = sh ? cv >> (64 - sh) : (cv >> 63);
@@ -1144,6 +1154,9 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
     const int64_t ea = __shfl_up(f.A, 1), et = __shfl_up(f.T, 1);
     CarryF excl = lane > 0 ? CarryF{ea, et} : pre;
     const bool have_excl = lane > 0 || have_pre;
+
+    // the guard's global atomics go out from wave 1 while wave 0 looks back
+    if (wv == 1 && lane == 0) publish_guard();
 
     // decoupled look-back, one wavefront.  status[2g] = state | A (aggregate)
     // or state | C (inclusive carry-out), status[2g+1] = state | T.  Values
@@ -1247,7 +1260,6 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
         else atomicOr(reinterpret_cast<unsigned long long*>(&p.w[li]), (unsigned long long)val);
     }
     }
-    if (tid == NT4 - 64) publish_guard();
 }
 
 }  // namespace tmul

@@ -143,13 +143,13 @@ bool launch_k2(uint32_t L2, const KParams& p, hipStream_t s)
 {
     dim3 g(k2_groups(p.L1, p.Lm));
     switch (L2) {
-    case 16: hipLaunchKernelGGL((k2_rows_pointwise<16>), g, dim3(NT), 0, s, p); return true;
-    case 32: hipLaunchKernelGGL((k2_rows_pointwise<32>), g, dim3(NT), 0, s, p); return true;
-    case 64: hipLaunchKernelGGL((k2_rows_pointwise<64>), g, dim3(NT), 0, s, p); return true;
-    case 128: hipLaunchKernelGGL((k2_rows_pointwise<128>), g, dim3(NT), 0, s, p); return true;
-    case 256: hipLaunchKernelGGL((k2_rows_pointwise<256>), g, dim3(NT), 0, s, p); return true;
-    case 512: hipLaunchKernelGGL((k2_rows_pointwise<512>), g, dim3(NT), 0, s, p); return true;
-    case 1024: hipLaunchKernelGGL((k2_rows_pointwise<1024>), g, dim3(NT), 0, s, p); return true;
+    case 16: hipLaunchKernelGGL((k2_rows_pointwise<16>), g, dim3(NT2), 0, s, p); return true;
+    case 32: hipLaunchKernelGGL((k2_rows_pointwise<32>), g, dim3(NT2), 0, s, p); return true;
+    case 64: hipLaunchKernelGGL((k2_rows_pointwise<64>), g, dim3(NT2), 0, s, p); return true;
+    case 128: hipLaunchKernelGGL((k2_rows_pointwise<128>), g, dim3(NT2), 0, s, p); return true;
+    case 256: hipLaunchKernelGGL((k2_rows_pointwise<256>), g, dim3(NT2), 0, s, p); return true;
+    case 512: hipLaunchKernelGGL((k2_rows_pointwise<512>), g, dim3(NT2), 0, s, p); return true;
+    case 1024: hipLaunchKernelGGL((k2_rows_pointwise<1024>), g, dim3(NT2), 0, s, p); return true;
     }
     return false;
 }
@@ -162,7 +162,7 @@ bool launch_mid(const KParams& p, hipStream_t s)
     const int W = (int)p.L2 < w_mid((int)p.Lm) ? (int)p.L2 : w_mid((int)p.Lm);
     dim3 g(p.L2 / W, p.L1, INV || p.zb == p.za ? 1 : 2);
 #define MIDW(LM, WW) \
-    if (p.Lm == LM && W == WW) { hipLaunchKernelGGL((k_mid_col<LM, WW, INV>), g, dim3(NT), 0, s, p); return true; }
+    if (p.Lm == LM && W == WW) { hipLaunchKernelGGL((k_mid_col<LM, WW, INV>), g, dim3(NTM), 0, s, p); return true; }
 #define MID(LM) MIDW(LM, 16) MIDW(LM, 32) MIDW(LM, 64)
     MID(2) MID(4) MID(8) MID(16) MID(32) MID(64) MIDW(128, 16) MIDW(128, 32) MIDW(256, 16)
 #undef MID
