@@ -419,7 +419,10 @@ __global__ __launch_bounds__(NT1) void k1_split_map_col(KParams p)
     constexpr int LB = k1_lb(KIND, B), LO = LB - 1, ND = k1_nd(W, KIND, B), NLW = k1_nlw(ND, B);
     constexpr int TE = padded(L1 * W);
     // limb windows staged in the tile area when they fit
-    constexpr bool STAGE = L1 * NLW * 8 <= TE * 16;
+    // staged rows are NLWP limbs apart: an odd stride puts the rows that
+    // neighbouring lanes read on different LDS banks
+    constexpr int NLWP = NLW | 1;
+    constexpr bool STAGE = L1 * NLWP * 8 <= TE * 16;
     static_assert(STAGE || B == 0, "compile-time digit sizes need staged limbs");
     constexpr int RPT = (L1 + NT1 - 1) / NT1;
     __shared__ double2 tile[TE];
@@ -462,7 +465,7 @@ __global__ __launch_bounds__(NT1) void k1_split_map_col(KParams p)
 #pragma unroll
         for (int q = 0; q < PL; q++) {
             const int e = tid + q * NT1;
-            if (L1 * NLW % NT1 == 0 || e < L1 * NLW) slimb[e] = lv[q];
+            if (L1 * NLW % NT1 == 0 || e < L1 * NLW) slimb[(e / NLW) * NLWP + e % NLW] = lv[q];
         }
     }
     __syncthreads();
@@ -491,7 +494,7 @@ __global__ __launch_bounds__(NT1) void k1_split_map_col(KParams p)
                     int64_t l0;
                     int rel0;
                     row_window(p, kf, l0, rel0);
-                    const uint64_t* sl = reinterpret_cast<const uint64_t*>(tile) + j1 * NLW;
+                    const uint64_t* sl = reinterpret_cast<const uint64_t*>(tile) + j1 * NLWP;
                     if constexpr (B > 0)
                         row_digits_fixed<ND, B, NLW>(sl, rel0, d);
                     else
