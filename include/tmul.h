@@ -110,6 +110,16 @@ typedef struct {
     uint64_t* w;
 } tm_request;
 
+/*
+ * Autotuner: time every FFT split the planner allows for (kind, n_bits)
+ * (the planner's own and each forced middle length Lm) on this device, on
+ * `stream`, with pseudo-random operands in buffers of its own (it allocates
+ * and frees them, and synchronises), and keep the fastest for later calls
+ * of this process.  The split changes neither N nor b, so results are the
+ * same as untuned.  *chosen (may be NULL) receives the tuned plan.
+ */
+tm_status tm_autotune(tm_kind kind, uint64_t n_bits, hipStream_t stream, tm_plan_info* chosen);
+
 /* Bytes of workspace a call of (kind, n_bits) needs; 0 if unsupported. */
 size_t tm_workspace_bytes(tm_kind kind, uint64_t n_bits);
 

@@ -17,7 +17,7 @@ import torch
 __all__ = ["mul", "mul_lo", "mul_hi", "mul_full", "mul_batched", "mul_checked",
            "coefficients", "profile_stages", "plan", "workspace_bytes", "Guard",
            "TmulError", "KINDS", "library_path", "prepare", "Server", "serve_trace",
-           "server_footprint"]
+           "server_footprint", "autotune"]
 
 KINDS = {"full": 0, "lo": 1, "hi": 2}
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -72,6 +72,8 @@ def _load():
     lib.tm_workspace_bytes_batched.argtypes = [P, SZ]
     lib.tm_workspace_bytes_batched.restype = SZ
     lib.tm_plan_query.argtypes = [I32, U64, ctypes.POINTER(_PlanInfo)]
+    lib.tm_autotune.argtypes = [I32, U64, P, ctypes.POINTER(_PlanInfo)]
+    lib.tm_autotune.restype = I32
     lib.tm_plan_query_guaranteed.argtypes = [I32, U64, ctypes.POINTER(_PlanInfo)]
     lib.tm_plan_query_guaranteed.restype = I32
     lib.tm_workspace_bytes_guaranteed.argtypes = [I32, U64]
@@ -328,6 +330,16 @@ def prepare(kind, n_bits, stream=None):
     st = stream if stream is not None else torch.cuda.current_stream()
     _check(_load().tm_prepare(_kind(kind), int(n_bits), ctypes.c_void_p(st.cuda_stream)),
            "prepare")
+
+
+def autotune(kind, n_bits, stream=None, device=None):
+    """Time the FFT splits of (kind, n_bits) on the GPU and keep the fastest
+    for this process (tm_autotune); returns the tuned plan."""
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    info = _PlanInfo()
+    _check(_load().tm_autotune(_kind(kind), int(n_bits), _stream_ptr(stream, dev),
+                               ctypes.byref(info)), "autotune")
+    return {k: getattr(info, k) for k, _ in _PlanInfo._fields_}
 
 
 def server_footprint(kind, n_bits):

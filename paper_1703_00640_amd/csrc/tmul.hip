@@ -9,6 +9,7 @@
 #include <mutex>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "tmul.h"
 #include "plan.hpp"
@@ -273,6 +274,19 @@ void fill_params(const Plan& P, const uint64_t* u, const uint64_t* v, uint64_t* 
     p.twm = tw.subm;
 }
 
+// Splits chosen by tm_autotune: (kind, n) -> middle length Lm (0: the
+// planner's own choice).  The split changes only the FFT schedule, not N or
+// b, so tuned and untuned calls return the same products.
+std::mutex g_tune_mu;
+std::map<std::pair<int, uint64_t>, uint32_t> g_tuned;
+
+uint32_t tuned_lm(tm_kind kind, uint64_t n)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(std::make_pair((int)kind, n));
+    return it == g_tuned.end() ? 0u : it->second;
+}
+
 tm_status plan_for(tm_kind kind, uint64_t n, Plan& P, int bt = 0, int bf = 0)
 {
     if (kind != TM_FULL && kind != TM_LO && kind != TM_HI) {
@@ -296,6 +310,7 @@ tm_status plan_for(tm_kind kind, uint64_t n, Plan& P, int bt = 0, int bf = 0)
         const char* e = getenv("TM_FORCE_LM");
         if (e && *e) flm = (uint32_t)atoi(e);
     }
+    if (!flm) flm = tuned_lm(kind, n);
     if (!make_plan((int)kind, n, bt, bf, P, flm)) {
         g_last_error = "unsupported size";
         return TM_ERR_UNSUPPORTED;
@@ -433,6 +448,86 @@ tm_status tm_plan_query(tm_kind kind, uint64_t n_bits, tm_plan_info* out)
     tm_status st = plan_for(kind, n_bits, P);
     if (st != TM_OK) return st;
     fill_info(kind, n_bits, P, out);
+    return TM_OK;
+}
+
+tm_status tm_autotune(tm_kind kind, uint64_t n_bits, hipStream_t stream, tm_plan_info* chosen)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned.erase(std::make_pair((int)kind, n_bits));
+    }
+    Plan P0;
+    tm_status st = plan_for(kind, n_bits, P0);
+    if (st != TM_OK) return st;
+    // candidates: the planner's split and every forced middle length
+    std::vector<uint32_t> cand{0};
+    for (uint32_t lm = 2; lm <= LM_MAX; lm *= 2) {
+        Plan Q;
+        if (make_plan((int)kind, n_bits, 0, 0, Q, lm) && Q.Lm != P0.Lm) cand.push_back(lm);
+    }
+    uint32_t best = 0;
+    if (cand.size() > 1) {
+        // pseudo-random operands (carry patterns like real data), own buffers
+        const size_t L = (n_bits + 63) / 64;
+        std::vector<uint64_t> h(2 * L);
+        uint64_t x = 0x9E3779B97F4A7C15ull;
+        for (auto& w : h) {
+            x ^= x << 13;
+            x ^= x >> 7;
+            x ^= x << 17;
+            w = x;
+        }
+        void *du = nullptr, *dw = nullptr, *dws = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        auto cleanup = [&]() {
+            if (du) (void)hipFree(du);
+            if (dw) (void)hipFree(dw);
+            if (dws) (void)hipFree(dws);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        };
+        const size_t wsb = P0.ws_bytes;
+        if (hipMalloc(&du, 2 * L * 8) != hipSuccess || hipMalloc(&dw, 2 * L * 8) != hipSuccess ||
+            hipMalloc(&dws, wsb) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+            hipEventCreate(&e1) != hipSuccess) {
+            cleanup();
+            return hip_fail(hipGetLastError(), "tm_autotune buffers");
+        }
+        if (hipMemcpy(du, h.data(), 2 * L * 8, hipMemcpyHostToDevice) != hipSuccess) {
+            cleanup();
+            return hip_fail(hipGetLastError(), "tm_autotune operands");
+        }
+        const uint64_t* u = static_cast<const uint64_t*>(du);
+        float best_ms = 0.0f;
+        for (uint32_t lm : cand) {
+            Plan Q;
+            if (!make_plan((int)kind, n_bits, 0, 0, Q, lm)) continue;
+            float tot = 0.0f;
+            for (int rep = 0; rep < 4 && st == TM_OK; rep++) {
+                if (rep == 1) st = hipEventRecord(e0, stream) == hipSuccess ? TM_OK : TM_ERR_HIP;
+                if (st == TM_OK)
+                    st = run(Q, static_cast<uint64_t*>(dw), u, u + L, dws, wsb, stream, nullptr, RUN,
+                             nullptr, nullptr, nullptr);
+            }
+            if (st == TM_OK && (hipEventRecord(e1, stream) != hipSuccess ||
+                                hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&tot, e0, e1) != hipSuccess))
+                st = TM_ERR_HIP;
+            if (st != TM_OK) break;
+            if (best_ms == 0.0f || tot < best_ms) {
+                best_ms = tot;
+                best = lm;
+            }
+        }
+        cleanup();
+        if (st != TM_OK) return st;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[std::make_pair((int)kind, n_bits)] = best;
+    }
+    if (chosen) return tm_plan_query(kind, n_bits, chosen);
     return TM_OK;
 }
 

@@ -296,6 +296,25 @@ def test_squaring_one_transform(monkeypatch, n, lm):
     assert oracle.hi_accepts(to_host(tm.mul("hi", du, du, n)), q, nz)
 
 
+def test_autotune_keeps_products():
+    """The autotuner picks one of the planner's FFT splits; products after
+    tuning equal the untuned ones bit for bit (the split changes neither N
+    nor b)."""
+    tm = _tm()
+    n = 1 << 20
+    u, v = inputs.operand_pair(n, 90)
+    before = {k: run_kind(k, u, v, n, guard=False)[0] for k in ("lo", "hi", "full")}
+    for k in ("lo", "hi", "full"):
+        p0 = tm.plan(k, n)
+        pt = tm.autotune(k, n)
+        say("[autotune] %s n=2^20 split %s -> %s" % (k, (p0["L1"], p0["Lm"], p0["L2"]),
+                                                     (pt["L1"], pt["Lm"], pt["L2"])))
+        assert (pt["N"], pt["b"]) == (p0["N"], p0["b"])
+        assert pt["L1"] * pt["Lm"] * pt["L2"] == pt["M"]
+        assert tm.plan(k, n)["Lm"] == pt["Lm"]
+        assert np.array_equal(run_kind(k, u, v, n, guard=False)[0], before[k])
+
+
 def test_config_n2_26_parity():
     """n = 2^26 (three-pass split chosen automatically): lo, hi, full vs the
     oracle."""

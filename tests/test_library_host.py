@@ -104,6 +104,7 @@ def test_invalid_arguments_rejected_without_gpu():
     info = tm._PlanInfo()
     assert lib.tm_plan_query(1, 0, ctypes.byref(info)) == 1
     assert lib.tm_status_string(3) == b"rounding guard tripped"
+    assert lib.tm_autotune(7, 4096, None, None) == 1
 
 
 def test_three_pass_split_for_large_n():
