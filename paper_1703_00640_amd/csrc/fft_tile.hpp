@@ -229,8 +229,11 @@ constexpr int pick_radix(int rem)
 
 // LDS tiles are padded by one element after every 16, which spreads the
 // power-of-two strides of the Stockham stages over the LDS banks.
-__device__ __forceinline__ int pidx(int e) { return e + (e >> 4); }
-constexpr int padded(int n) { return n + (n >> 4) + 1; }
+#ifndef TM_PAD_SHIFT
+#define TM_PAD_SHIFT 4
+#endif
+__device__ __forceinline__ int pidx(int e) { return TM_PAD_SHIFT ? e + (e >> TM_PAD_SHIFT) : e; }
+constexpr int padded(int n) { return TM_PAD_SHIFT ? n + (n >> TM_PAD_SHIFT) + 1 : n; }
 
 // Element (j, c) of the tile: sequence c, position j.
 //   COLS: sequences interleaved (index j*NB + c)  - column tiles
