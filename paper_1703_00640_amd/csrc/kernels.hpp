@@ -599,7 +599,9 @@ __device__ __forceinline__ void k2_rows_of(uint32_t g, uint32_t L1, uint32_t Lm,
 }
 
 template <int L2>
-__global__ __launch_bounds__(NT2) void k2_rows_pointwise(KParams p)
+// rows of up to 512 points fit four workgroups per CU in LDS; the second
+// bound (waves per SIMD) keeps their registers within that occupancy
+__global__ __launch_bounds__(NT2, L2 <= 512 ? 4 : 2) void k2_rows_pointwise(KParams p)
 {
     // rows 0,1: operands u,v at row (k1, km); rows 2,3: at the mirror row
     __shared__ double2 rows[padded(4 * L2)];
