@@ -1,9 +1,12 @@
 // HIP kernels of the truncated / full product path (gfx950, FP64).
 //
-// One multiplication is four launches on one stream:
+// One multiplication is four launches on one stream (six with the middle
+// pass of the three-pass split):
 //   K1 split + ring map + forward column pass   (Alg. low/high steps 2-3,
 //      first half of the forward FFTs of step 4; Alg. full steps 2-3)
+//   [k_mid_col forward middle pass]
 //   K2 forward row pass, pointwise product, inverse row pass (step 4)
+//   [k_mid_col inverse middle pass]
 //   K3 inverse column pass                       (end of step 4)
 //   K4 back-map, rounding, guard, carry propagation, extraction (steps 5-6)
 //
@@ -11,10 +14,16 @@
 // M = N/2: a real sequence G is packed as y_m = G_2m + i G_2m+1.  The two
 // operands are transformed separately; their length-N real spectra are
 // recovered from the bins k and M-k of the packed transforms, multiplied,
-// and repacked for a length-M inverse, all in K2.  M = L1 * L2 is split
-// four-step style: K1/K3 do the L1-point column DFTs (stride L2), K2 the
-// L2-point row DFTs; the spectrum stays in the row-major "scrambled" order
-// (position k1*L2 + k2 holds bin k1 + L1*k2), so no transpose pass exists.
+// and repacked for a length-M inverse, all in K2.  M = L1 * Lm * L2 is split
+// four-step style: K1/K3 do the L1-point column DFTs (stride R = Lm L2), the
+// middle pass the Lm-point DFTs inside each row, K2 the L2-point row DFTs;
+// the spectrum stays in a "scrambled" order (row (k1, km), position k2
+// holds bin k1 + L1 (km + Lm k2)), so no transpose pass exists.
+//
+// Build-time knobs (defaults are the measured best on MI355X): TM_NT1,
+// TM_NT2, TM_NT3, TM_NT4, TM_NTM threads per workgroup of K1, K2, K3, K4 and
+// the middle pass; TM_TILE1 / TM_TILE3 complex elements per K1 / K3 column
+// tile; TM_DPT coefficients per K4 thread; TM_PAD_SHIFT LDS tile padding.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
