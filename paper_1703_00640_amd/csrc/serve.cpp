@@ -124,7 +124,8 @@ struct tm_server {
     std::vector<int> load;
     std::vector<hipEvent_t> spare_events;
     std::deque<Job> waiting;
-    std::vector<Job> running;
+    std::vector<std::deque<Job>> running;  // per stream, in launch order
+    size_t n_running = 0;
     std::deque<std::pair<uint64_t, tm_status>> finished;
     uint64_t next_id = 1;
     size_t max_inflight = 0;
@@ -169,7 +170,7 @@ tm_status launch(tm_server* s, Job& j)
 void admit(tm_server* s)
 {
     size_t reserved = 0;
-    for (auto it = s->waiting.begin(); it != s->waiting.end() && s->running.size() < s->max_inflight;) {
+    for (auto it = s->waiting.begin(); it != s->waiting.end() && s->n_running < s->max_inflight;) {
         Job& j = *it;
         size_t off;
         const bool room = s->pool.free_bytes() >= reserved + j.lay.total;
@@ -189,7 +190,8 @@ void admit(tm_server* s)
                 s->finished.emplace_back(j.id, r);
             } else {
                 s->load[best]++;
-                s->running.push_back(j);
+                s->running[best].push_back(j);
+                s->n_running++;
             }
             it = s->waiting.erase(it);
         } else {
@@ -199,21 +201,22 @@ void admit(tm_server* s)
     }
 }
 
+// Work on a stream completes in launch order, so only the oldest request of
+// each stream needs an event query (or a wait, when block is set).
 void retire(tm_server* s, bool block)
 {
-    for (size_t k = 0; k < s->running.size();) {
-        Job& j = s->running[k];
-        hipError_t e = block ? hipEventSynchronize(j.done) : hipEventQuery(j.done);
-        if (e == hipErrorNotReady) {
-            ++k;
-            continue;
+    for (auto& q : s->running) {
+        while (!q.empty()) {
+            Job& j = q.front();
+            hipError_t e = block ? hipEventSynchronize(j.done) : hipEventQuery(j.done);
+            if (e == hipErrorNotReady) break;
+            s->finished.emplace_back(j.id, e == hipSuccess ? TM_OK : TM_ERR_HIP);
+            s->pool.release(j.off, j.lay.total);
+            s->load[j.stream]--;
+            s->spare_events.push_back(j.done);
+            q.pop_front();
+            s->n_running--;
         }
-        s->finished.emplace_back(j.id, e == hipSuccess ? TM_OK : TM_ERR_HIP);
-        s->pool.release(j.off, j.lay.total);
-        s->load[j.stream]--;
-        s->spare_events.push_back(j.done);
-        s->running[k] = s->running.back();
-        s->running.pop_back();
     }
 }
 
@@ -247,6 +250,7 @@ tm_status tm_server_create(size_t pool_bytes, int n_streams, int max_inflight, t
         }
         s->streams.push_back(st);
         s->load.push_back(0);
+        s->running.emplace_back();
     }
     *out = s;
     return TM_OK;
@@ -285,13 +289,13 @@ int tm_server_poll(tm_server* s, uint64_t* ids, tm_status* status, int cap)
 
 size_t tm_server_pending(const tm_server* s)
 {
-    return s ? s->waiting.size() + s->running.size() : 0;
+    return s ? s->waiting.size() + s->n_running : 0;
 }
 
 tm_status tm_server_drain(tm_server* s)
 {
     if (!s) return TM_ERR_INVALID;
-    while (!s->waiting.empty() || !s->running.empty()) {
+    while (!s->waiting.empty() || s->n_running) {
         retire(s, s->waiting.empty());
         admit(s);
     }
@@ -301,8 +305,10 @@ tm_status tm_server_drain(tm_server* s)
 void tm_server_destroy(tm_server* s)
 {
     if (!s) return;
-    for (auto& j : s->running) (void)hipEventSynchronize(j.done);
-    for (auto& j : s->running) (void)hipEventDestroy(j.done);
+    for (auto& q : s->running)
+        for (auto& j : q) (void)hipEventSynchronize(j.done);
+    for (auto& q : s->running)
+        for (auto& j : q) (void)hipEventDestroy(j.done);
     for (auto e : s->spare_events) (void)hipEventDestroy(e);
     for (auto st : s->streams) (void)hipStreamDestroy(st);
     if (s->base) (void)hipFree(s->base);
