@@ -28,7 +28,8 @@
  *   HIP call (per thread).
  * - The library keeps one device-side cache per (device, transform length):
  *   the FFT twiddle tables, built on first use (this first call synchronises
- *   its stream once).  tm_release_caches() frees them.
+ *   its stream once), and a few pinned host buffers for the launch metadata
+ *   of packed batches.  tm_release_caches() frees them.
  */
 #ifndef TMUL_H
 #define TMUL_H
@@ -153,17 +154,52 @@ tm_status tm_mul_hi(uint64_t* w, const uint64_t* u, const uint64_t* v, uint64_t 
                     void* workspace, size_t workspace_bytes, hipStream_t stream,
                     tm_guard* guard_dev);
 
-/* Workspace for a batch: the largest single-request workspace. */
+/*
+ * Batches of independent multiplications in packed launches.  Every stage
+ * of the method (K1 split + map + column pass, the middle passes, K2 rows +
+ * pointwise product, K3, K4 back-map + carry) runs as one launch per kernel
+ * instance over all requests whose plans select that instance, instead of
+ * one launch per request: a batch of mixed sizes and kinds costs a handful
+ * of launches.  Each request has its own plan, workspace and guard, so its
+ * result is bit-identical to the same call of tm_mul.  The requests must be
+ * independent: no request may read another's output, and outputs must not
+ * overlap any operand or each other.
+ */
+
+/* Workspace for tm_mul_batched: the sum of the requests' workspaces (each
+ * rounded up to 256 bytes) plus tm_batch_meta_bytes(count); 0 if a request
+ * is unsupported. */
 size_t tm_workspace_bytes_batched(const tm_request* reqs, size_t count);
 
 /*
  * Run `count` requests (host array of descriptors with device pointers) on
- * one stream, in order, sharing one workspace of
- * tm_workspace_bytes_batched() bytes.  guards_dev: device array of `count`
- * tm_guard, or NULL.
+ * one stream in packed launches, with one workspace of
+ * tm_workspace_bytes_batched() bytes (256-byte aligned) carved into the
+ * requests' workspaces and the metadata area.  guards_dev: device array of
+ * `count` tm_guard, or NULL.
  */
 tm_status tm_mul_batched(const tm_request* reqs, size_t count, void* workspace,
                          size_t workspace_bytes, hipStream_t stream, tm_guard* guards_dev);
+
+/* Bytes of the device metadata area of a packed batch of `count` requests
+ * (per-request parameters and the launch tables). */
+size_t tm_batch_meta_bytes(size_t count);
+
+/*
+ * tm_mul_batched with caller-placed memory: workspaces[i] (device, 256-byte
+ * aligned, workspace_bytes[i] >= tm_workspace_bytes(kind, n) bytes) is
+ * request i's workspace; `meta` (device, 256-byte aligned, meta_bytes >=
+ * tm_batch_meta_bytes(count)) receives the launch metadata, uploaded by the
+ * library from a pinned host buffer of its own on `stream`.  guards_dev:
+ * host array of `count` device pointers (an entry may be NULL: that guard
+ * stays in the workspace), or NULL.  The metadata area and the workspaces
+ * must stay untouched until the batch has completed on the stream.
+ * TM_ERR_INVALID (nothing launched) for a null pointer, a misaligned or too
+ * small area.
+ */
+tm_status tm_mul_packed(const tm_request* reqs, size_t count, void* const* workspaces,
+                        const size_t* workspace_bytes, void* meta, size_t meta_bytes,
+                        hipStream_t stream, tm_guard* const* guards_dev);
 
 /*
  * Like tm_mul, then synchronises the stream and reads the guard.  If it
@@ -235,21 +271,23 @@ tm_status tm_prepare(tm_kind kind, uint64_t n_bits, hipStream_t stream);
  * Serving: continuous batching on the current device.
  *
  * A server owns one device memory pool of pool_bytes (allocated at
- * creation), n_streams HIP streams and max_inflight request slots (0: 8 per
- * stream).  Requests carry HOST pointers
- * (tm_request.u, .v: n_bits-bit operands, read until the request
- * completes; .w: result buffer of the tm_mul layout); pinned host memory
- * lets the copies overlap.  Requests wait in submission order and each is
- * admitted once a slot is free and its footprint (tm_server_footprint:
- * operands, result, guard, workspace) can be carved out of the pool; it
- * then runs on the
- * stream with the fewest requests in flight (copy in, tm_mul, copy out).
- * A request that does not fit reserves the bytes it waits for: requests
- * behind it pass it only within the remaining free bytes.
- * tm_server_poll retires finished requests, frees their memory and admits
- * waiting ones, so requests that arrive while others run join as memory
- * frees up, and their work overlaps on the device.  Results equal tm_mul's
- * for the same (kind, n_bits) (the plan depends on them only).  A server is
+ * creation), n_streams HIP streams and max_inflight request slots (0: 128
+ * per stream).  Requests carry HOST pointers (tm_request.u, .v: n_bits-bit
+ * operands, read until the request completes; .w: result buffer of the
+ * tm_mul layout); pinned host memory lets the copies overlap.  Requests
+ * wait in submission order.  Whenever a stream has fewer than two batches
+ * in flight, the waiting requests that fit are admitted as one batch of up
+ * to 64: each gets its footprint (tm_server_footprint: operands, result,
+ * workspace) carved out of the pool, and the batch gets one block for its
+ * launch metadata and guards.  A batch is operand copies, one packed
+ * multiplication call (tm_mul_packed; tm_mul for a batch of one), result
+ * copies, one guard copy and one completion event.  A request that does
+ * not fit reserves the bytes it waits for: requests behind it pass it only
+ * within the remaining free bytes.  tm_server_poll retires finished
+ * batches, frees their memory and admits waiting requests, so requests that
+ * arrive while others run join the next batch as a stream and memory free
+ * up, and their work overlaps on the device.  Results equal tm_mul's for
+ * the same (kind, n_bits) (the plan depends on them only).  A server is
  * used from one host thread at a time.  The throughput / latency workload
  * of a whole arrival trace runs through tm_serve_trace.
  */
@@ -259,7 +297,7 @@ size_t tm_server_footprint(tm_kind kind, uint64_t n_bits);  /* 0 if unsupported 
 tm_status tm_server_create(size_t pool_bytes, int n_streams, int max_inflight, tm_server** out);
 /* Queue one request (copied; guard_host: host tm_guard written on
  * completion, or NULL).  *id identifies it in tm_server_poll.
- * TM_ERR_INVALID if its footprint exceeds the pool. */
+ * TM_ERR_INVALID if its footprint and one batch block exceed the pool. */
 tm_status tm_server_submit(tm_server* s, const tm_request* req, tm_guard* guard_host, uint64_t* id);
 /* Retire finished requests and admit waiting ones; writes up to cap
  * (id, status) pairs of finished requests and returns their number (-1 on

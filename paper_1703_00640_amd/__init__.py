@@ -84,6 +84,10 @@ def _load():
     for name in ("tm_mul_full", "tm_mul_lo", "tm_mul_hi"):
         getattr(lib, name).argtypes = [P, P, P, U64, P, SZ, P, P]
     lib.tm_mul_batched.argtypes = [P, SZ, P, SZ, P, P]
+    lib.tm_batch_meta_bytes.argtypes = [SZ]
+    lib.tm_batch_meta_bytes.restype = SZ
+    lib.tm_mul_packed.argtypes = [P, SZ, P, P, P, SZ, P, P]
+    lib.tm_mul_packed.restype = I32
     lib.tm_mul_checked.argtypes = [I32, P, P, P, U64, P, SZ, P, ctypes.POINTER(Guard)]
     lib.tm_coefficients.argtypes = [I32, P, P, U64, P, P, U64, P, SZ, P, P]
     lib.tm_profile_stages.argtypes = [I32, P, P, P, U64, P, SZ, P,
@@ -239,8 +243,10 @@ def mul_full(u, v, n_bits, **kw):
 
 
 def mul_batched(requests, workspace=None, stream=None, guards=None):
-    """requests: list of (kind, u, v, n_bits, out) with device tensors; runs
-    them in order on one stream with a shared workspace."""
+    """requests: list of (kind, u, v, n_bits, out) with device tensors of
+    independent multiplications; runs them on one stream in packed launches
+    (one launch per stage and kernel instance), each request with its own
+    slice of one workspace."""
     if not requests:
         return
     arr = (_Request * len(requests))()

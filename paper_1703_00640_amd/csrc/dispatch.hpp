@@ -52,9 +52,32 @@ bool launch_k1(uint32_t L1, const KParams& p, hipStream_t s)
     return fixed_b(KIND, p) ? launch_k1_b<KIND, BF>(L1, p, s) : launch_k1_b<KIND, 0>(L1, p, s);
 }
 
+// Packed launch of one K1 instance over the requests of group g (`blocks`
+// workgroups in total); fb: the requests' common fixed_b().
+template <int KIND, int B>
+bool launch_k1g_b(uint32_t L1, const Group& g, uint32_t blocks, hipStream_t s)
+{
+    switch (L1) {
+#define X(V) \
+    case V: hipLaunchKernelGGL((k1_split_map_col_g<V, w1_for(V), KIND, B>), dim3(blocks), dim3(NT1), 0, s, g); return true;
+        TM_L1_LIST(X)
+#undef X
+    }
+    return false;
+}
+
+template <int KIND, int BF>
+bool launch_k1g(uint32_t L1, int fb, const Group& g, uint32_t blocks, hipStream_t s)
+{
+    return fb ? launch_k1g_b<KIND, BF>(L1, g, blocks, s) : launch_k1g_b<KIND, 0>(L1, g, blocks, s);
+}
+
 // defined in k1_full.hip, k1_lo.hip, k1_hi.hip
 bool launch_k1_full(uint32_t L1, const KParams& p, hipStream_t s);
 bool launch_k1_lo(uint32_t L1, const KParams& p, hipStream_t s);
 bool launch_k1_hi(uint32_t L1, const KParams& p, hipStream_t s);
+bool launch_k1g_full(uint32_t L1, int fb, const Group& g, uint32_t blocks, hipStream_t s);
+bool launch_k1g_lo(uint32_t L1, int fb, const Group& g, uint32_t blocks, hipStream_t s);
+bool launch_k1g_hi(uint32_t L1, int fb, const Group& g, uint32_t blocks, hipStream_t s);
 
 }  // namespace tmul

@@ -117,6 +117,71 @@ struct KParams {
     double* dbg_x;
 };
 
+// ------------------------------------------------------- workgroup indices
+
+// A workgroup's position in its own multiplication's grid.  A plain launch
+// takes it from the hardware ids; a packed launch (several multiplications
+// in one 1-D grid) from its request's entry in the group table.
+struct Blk {
+    uint32_t x, y, z;  // workgroup index
+    uint32_t nx, ny;   // grid extent in x and y
+};
+
+__device__ __forceinline__ Blk blk_hw()
+{
+    return Blk{blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y};
+}
+
+// One entry per request of a packed launch: its first workgroup in the 1-D
+// grid, its own grid extent (nx, ny; nz follows from the block count) and
+// the index of its parameters.  Entries are in increasing `start` order,
+// start[0] = 0, at most 64 per launch.
+struct GroupEnt {
+    uint32_t start, nx, ny, pi;
+};
+struct Group {
+    const KParams* ps;
+    const GroupEnt* ent;
+    uint32_t nr;
+};
+constexpr int GROUP_MAX = 64;
+
+// The group table is written by the host before the launch and only read by
+// the kernels, so its uniform entry is loaded through the constant address
+// space (a scalar load).
+typedef const __attribute__((address_space(4))) GroupEnt* GroupEntC;
+
+// Parameters of request pi of a packed launch, read in place (a private
+// copy would go to scratch memory where the maps index its tables).
+__device__ __forceinline__ const KParams& group_params(const Group& g, uint32_t pi)
+{
+    return g.ps[pi];
+}
+
+// The request of this workgroup: one entry per lane, a ballot of the
+// entries that start at or before this workgroup, and the last of them.
+__device__ __forceinline__ Blk group_block(const Group& g, uint32_t& pi)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t st = lane < g.nr ? g.ent[lane].start : 0xffffffffu;
+    const uint64_t m = __ballot(st <= blockIdx.x);
+    const uint32_t r = (uint32_t)__builtin_amdgcn_readfirstlane(__popcll(m) - 1);
+#if defined(__HIP_DEVICE_COMPILE__)
+    const GroupEnt e = ((GroupEntC)g.ent)[r];
+#else
+    const GroupEnt e = g.ent[r];
+#endif
+    const uint32_t local = blockIdx.x - e.start;
+    Blk b;
+    b.nx = e.nx;
+    b.ny = e.ny;
+    b.x = local % e.nx;
+    b.y = (local / e.nx) % e.ny;
+    b.z = local / (e.nx * e.ny);
+    pi = e.pi;
+    return b;
+}
+
 // ---------------------------------------------------------------- digits
 
 // bits [pos, pos+nb) of (x mod 2^n); positions outside [0, n) read as zero
@@ -421,7 +486,7 @@ __device__ __forceinline__ void row_map_edge(const KParams& p, uint32_t m0, doub
 // (M = L1 R, R = Lm L2; element (k1, col) is point m = k1 R + col).
 // B: compile-time digit size (0: runtime p.b).
 template <int L1, int W, int KIND, int B>
-__global__ __launch_bounds__(NT1) void k1_split_map_col(KParams p)
+__device__ __forceinline__ void k1_body(const KParams& p, const Blk bk)
 {
     static_assert(L1 * W <= TILE1, "tile too large");
     constexpr int PER = (L1 * W + NT1 - 1) / NT1;
@@ -437,11 +502,11 @@ __global__ __launch_bounds__(NT1) void k1_split_map_col(KParams p)
     __shared__ double2 tile[TE];
     __shared__ double2 twl[twl_size(L1)];
     __shared__ double s_th[LMAX + 8];  // terms of theta (high product, tile 0)
-    const int op = blockIdx.y;
+    const int op = bk.y;
     const uint64_t* x = op ? p.v : p.u;
     double2* dst = op ? p.zb : p.za;
     const uint32_t L2 = p.R;  // row length of the L1 x R matrix
-    const uint32_t c0 = xcd_tile(blockIdx.x, gridDim.x) * W;
+    const uint32_t c0 = xcd_tile(bk.x, bk.nx) * W;
     const int tid = threadIdx.x;
 
     load_twl<L1, NT1>(twl, p.tw1);
@@ -453,8 +518,8 @@ __global__ __launch_bounds__(NT1) void k1_split_map_col(KParams p)
     const uint32_t es = (uint32_t)((uint64_t)colt * (uint32_t)(NT1 / W) % p.M);
     const double2 tb0 = p.tw.lo[eb & p.tw.mask], tb1 = p.tw.hi[eb >> p.tw.shift];
     const double2 ts0 = p.tw.lo[es & p.tw.mask], ts1 = p.tw.hi[es >> p.tw.shift];
-    if (op == 0) clear_state(p, blockIdx.x * NT1 + tid, gridDim.x * NT1);
-    if (KIND == K_HI && blockIdx.x == 0 && tid <= (int)p.jmax && tid <= (int)p.N)
+    if (op == 0) clear_state(p, bk.x * NT1 + tid, bk.nx * NT1);
+    if (KIND == K_HI && bk.x == 0 && tid <= (int)p.jmax && tid <= (int)p.N)
         s_th[tid] = ldexp((double)bal_digit(p, x, (int64_t)p.N - tid, p.digits, true), -tid * p.b);
     if constexpr (STAGE) {
         uint64_t* slimb = reinterpret_cast<uint64_t*>(tile);
@@ -478,12 +543,12 @@ __global__ __launch_bounds__(NT1) void k1_split_map_col(KParams p)
         }
     }
     __syncthreads();
-    if (KIND == K_HI && blockIdx.x == 0 && tid == 0) {
+    if (KIND == K_HI && bk.x == 0 && tid == 0) {
         // theta = rho^-N F(rho), rho ~ 2^b: sum_j 2^(-jb) F_(N-j), j <= jmax
         double th = 0.0;
         for (int j = 0; j <= (int)p.jmax && j <= (int)p.N; j++) th += s_th[j];
         p.theta[op] = th;
-        if (gridDim.y == 1) p.theta[1] = th;  // squaring: theta_V = theta_U
+        if (bk.ny == 1) p.theta[1] = th;  // squaring: theta_V = theta_U
     }
     // rows away from index 0 (and, for the full product, from the top digit)
     // take the fast path; the others the term-by-term one
@@ -554,6 +619,21 @@ __global__ __launch_bounds__(NT1) void k1_split_map_col(KParams p)
     }
 }
 
+template <int L1, int W, int KIND, int B>
+__global__ __launch_bounds__(NT1) void k1_split_map_col(KParams p)
+{
+    k1_body<L1, W, KIND, B>(p, blk_hw());
+}
+
+template <int L1, int W, int KIND, int B>
+__global__ __launch_bounds__(NT1) void k1_split_map_col_g(Group g)
+{
+    uint32_t pi;
+    const Blk bk = group_block(g, pi);
+    const KParams& p = group_params(g, pi);
+    k1_body<L1, W, KIND, B>(p, bk);
+}
+
 // ------------------------------------------------------------------- K2
 
 // Spectra of the two real operands from the packed transforms, product, and
@@ -608,16 +688,14 @@ __device__ __forceinline__ void k2_rows_of(uint32_t g, uint32_t L1, uint32_t Lm,
 }
 
 template <int L2>
-// rows of up to 512 points fit four workgroups per CU in LDS; the second
-// bound (waves per SIMD) keeps their registers within that occupancy
-__global__ __launch_bounds__(NT2, L2 <= 512 ? 4 : 2) void k2_rows_pointwise(KParams p)
+__device__ __forceinline__ void k2_body(const KParams& p, const Blk bk)
 {
     // rows 0,1: operands u,v at row (k1, km); rows 2,3: at the mirror row
     __shared__ double2 rows[padded(4 * L2)];
     __shared__ double2 twl[twl_size(L2)];
     const uint32_t L1 = p.L1, Lm = p.Lm;
     uint32_t k1, km;
-    k2_rows_of(blockIdx.x, L1, Lm, k1, km);
+    k2_rows_of(bk.x, L1, Lm, k1, km);
     const uint32_t k1m = k1 ? L1 - k1 : 0;
     const uint32_t kmm = k1 ? Lm - 1 - km : (km ? Lm - km : 0);
     const uint32_t rowa = k1 * Lm + km, rowb = k1m * Lm + kmm;
@@ -684,6 +762,23 @@ __global__ __launch_bounds__(NT2, L2 <= 512 ? 4 : 2) void k2_rows_pointwise(KPar
     }
 }
 
+// rows of up to 512 points fit four workgroups per CU in LDS; the second
+// bound (waves per SIMD) keeps their registers within that occupancy
+template <int L2>
+__global__ __launch_bounds__(NT2, L2 <= 512 ? 4 : 2) void k2_rows_pointwise(KParams p)
+{
+    k2_body<L2>(p, blk_hw());
+}
+
+template <int L2>
+__global__ __launch_bounds__(NT2, L2 <= 512 ? 4 : 2) void k2_rows_pointwise_g(Group g)
+{
+    uint32_t pi;
+    const Blk bk = group_block(g, pi);
+    const KParams& p = group_params(g, pi);
+    k2_body<L2>(p, bk);
+}
+
 // ------------------------------------------------------------ middle pass
 
 // Middle column pass of the three-pass split (Lm > 1): inside each row k1
@@ -692,15 +787,15 @@ __global__ __launch_bounds__(NT2, L2 <= 512 ? 4 : 2) void k2_rows_pointwise(KPar
 // on both operands.  Inverse: exp(+2 pi i j2 km / R), then inverse DFT, on
 // the product.  grid = (L2 / W, L1, operands).
 template <int LM, int W, bool INV>
-__global__ __launch_bounds__(NTM) void k_mid_col(KParams p)
+__device__ __forceinline__ void mid_body(const KParams& p, const Blk bk)
 {
     constexpr int PER = (LM * W + NTM - 1) / NTM;
     static_assert(NTM % W == 0, "W must divide NTM");
     __shared__ double2 tile[padded(LM * W)];
     __shared__ double2 twl[twl_size(LM)];
     const uint32_t L2 = p.L2;
-    const uint32_t c0 = xcd_tile(blockIdx.x, gridDim.x) * W;
-    double2* a = (blockIdx.z ? p.zb : p.za) + (size_t)blockIdx.y * p.R;
+    const uint32_t c0 = xcd_tile(bk.x, bk.nx) * W;
+    double2* a = (bk.z ? p.zb : p.za) + (size_t)bk.y * p.R;
     const int tid = threadIdx.x;
     load_twl<LM, NTM>(twl, p.twm);
     // twiddle exponents on the R-th root, as exponents of the M-th root (x L1)
@@ -735,15 +830,30 @@ __global__ __launch_bounds__(NTM) void k_mid_col(KParams p)
     }
 }
 
+template <int LM, int W, bool INV>
+__global__ __launch_bounds__(NTM) void k_mid_col(KParams p)
+{
+    mid_body<LM, W, INV>(p, blk_hw());
+}
+
+template <int LM, int W, bool INV>
+__global__ __launch_bounds__(NTM) void k_mid_col_g(Group g)
+{
+    uint32_t pi;
+    const Blk bk = group_block(g, pi);
+    const KParams& p = group_params(g, pi);
+    mid_body<LM, W, INV>(p, bk);
+}
+
 // ------------------------------------------------------------------- K3
 
 template <int L1, int W>
-__global__ __launch_bounds__(NT3) void k3_col_inverse(KParams p)
+__device__ __forceinline__ void k3_body(const KParams& p, const Blk bk)
 {
     __shared__ double2 tile[padded(L1 * W)];
     __shared__ double2 twl[twl_size(L1)];
     const uint32_t L2 = p.R;  // row length of the L1 x R matrix
-    const uint32_t c0 = xcd_tile(blockIdx.x, gridDim.x) * W;
+    const uint32_t c0 = xcd_tile(bk.x, bk.nx) * W;
     load_twl<L1, NT3>(twl, p.tw1);
     constexpr int PER = (L1 * W + NT3 - 1) / NT3;
     static_assert(NT3 % W == 0, "W must divide NT3");
@@ -776,6 +886,21 @@ __global__ __launch_bounds__(NT3) void k3_col_inverse(KParams p)
         const int e = threadIdx.x + q * NT3;
         if (L1 * W % NT3 == 0 || e < L1 * W) p.za[(size_t)(e / W) * L2 + c0 + e % W] = tile[pidx(e)];
     }
+}
+
+template <int L1, int W>
+__global__ __launch_bounds__(NT3) void k3_col_inverse(KParams p)
+{
+    k3_body<L1, W>(p, blk_hw());
+}
+
+template <int L1, int W>
+__global__ __launch_bounds__(NT3) void k3_col_inverse_g(Group g)
+{
+    uint32_t pi;
+    const Blk bk = group_block(g, pi);
+    const KParams& p = group_params(g, pi);
+    k3_body<L1, W>(p, bk);
 }
 
 // ------------------------------------------------------------------- K4
@@ -940,7 +1065,7 @@ __device__ __forceinline__ void back_chain(const KParams& p, const double* sq, i
 }
 
 template <int KIND, bool DIAG, int B>
-__global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
+__device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
 {
     constexpr int NW = NT4 / 64;
     constexpr int LB = KIND == K_FULL ? 1 : B ? LB_FIXED : LMAX;
@@ -957,7 +1082,7 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
     const double* q = reinterpret_cast<const double*>(p.za);
 
     if (tid == 0) {
-        s_g = DIAG ? blockIdx.x : atomicAdd(p.ticket, 1u);
+        s_g = DIAG ? bk.x : atomicAdd(p.ticket, 1u);
         if (KIND == K_HI) s_thW = p.theta[0] * p.theta[1];
     }
     __syncthreads();
@@ -1274,6 +1399,21 @@ __global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
         else atomicOr(reinterpret_cast<unsigned long long*>(&p.w[li]), (unsigned long long)val);
     }
     }
+}
+
+template <int KIND, bool DIAG, int B>
+__global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
+{
+    k4_body<KIND, DIAG, B>(p, blk_hw());
+}
+
+template <int KIND, int B>
+__global__ __launch_bounds__(NT4) void k4_backmap_carry_g(Group g)
+{
+    uint32_t pi;
+    const Blk bk = group_block(g, pi);
+    const KParams& p = group_params(g, pi);
+    k4_body<KIND, false, B>(p, bk);
 }
 
 }  // namespace tmul

@@ -1,18 +1,19 @@
 // Continuous-batching server of the truncated-multiplication library (see
 // the tm_server_* declarations in include/tmul.h).
 //
-// A server owns one device memory pool, a few HIP streams and a number of
-// request slots.  Requests carry host operand / result buffers.  They wait
-// in arrival order; a request is admitted as soon as a slot is free and its
-// device footprint (operands, result, guard, workspace) can be carved out of
-// the pool, and then runs on the
-// stream with the fewest requests in flight: operands in, tm_mul, result
-// and guard out, completion event.  Polling retires finished requests,
-// returns their memory and admits more, so requests that arrive while others
-// run join the device as soon as memory frees up, and their work overlaps
-// on the device through the streams.  A request that does not fit reserves
-// the bytes it is waiting for, so smaller requests behind it can pass it
-// only within the remaining space (no starvation of large requests).
+// A server owns one device memory pool and a few HIP streams.  Requests
+// carry host operand / result buffers and wait in arrival order.  Whenever
+// a stream has room for another batch, the waiting requests whose device
+// footprint (operands, result, workspace) can be carved out of the pool are
+// admitted together, up to kMaxBatch, and run as one batch on that stream:
+// operands in, one packed multiplication call (every stage one launch per
+// kernel instance), results and guards out, one completion event.  Polling
+// retires finished batches, returns their memory and admits more, so
+// requests that arrive while others run gather into the next batch, and
+// batches on different streams overlap on the device.  A request that does
+// not fit reserves the bytes it is waiting for, so smaller requests behind
+// it can pass it only within the remaining space (no starvation of large
+// requests).
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -81,8 +82,8 @@ private:
 };
 
 struct Layout {
-    size_t u, v, w, g, ws, total;  // offsets inside the request's block
-    size_t ub, wb, wsb;            // bytes of u (= v), w and workspace
+    size_t u, v, w, ws, total;  // offsets inside the request's block
+    size_t ub, wb, wsb;         // bytes of u (= v), w and workspace
 };
 
 bool layout_for(tm_kind kind, uint64_t n, Layout& l)
@@ -98,7 +99,6 @@ bool layout_for(tm_kind kind, uint64_t n, Layout& l)
     l.u = o; o = align_up(o + l.ub);
     l.v = o; o = align_up(o + l.ub);
     l.w = o; o = align_up(o + l.wb);
-    l.g = o; o = align_up(o + sizeof(tm_guard));
     l.total = o;
     return true;
 }
@@ -109,10 +109,24 @@ struct Job {
     tm_guard* guard_host;
     Layout lay;
     size_t off = 0;
-    int stream = -1;
-    hipEvent_t done = nullptr;
     double t_submit = 0.0;
 };
+
+// Requests launched together: one packed multiplication call, one metadata
+// and guard block in the pool, one completion event.
+struct Batch {
+    std::vector<Job> jobs;
+    int stream = -1;
+    size_t meta_off = 0;
+    hipEvent_t done = nullptr;
+    tm_guard* guards_host = nullptr;  // pinned staging of the batch's guards
+};
+
+constexpr size_t kMaxBatch = 64;
+
+// Pool block of a batch: launch metadata, then the guards of its requests.
+size_t batch_guard_offset() { return align_up(tm_batch_meta_bytes(kMaxBatch)); }
+size_t batch_block_bytes() { return batch_guard_offset() + align_up(kMaxBatch * sizeof(tm_guard)); }
 
 }  // namespace
 
@@ -121,10 +135,11 @@ struct tm_server {
     char* base = nullptr;
     Pool pool;
     std::vector<hipStream_t> streams;
-    std::vector<int> load;
+    std::vector<int> load;                 // requests in flight per stream
     std::vector<hipEvent_t> spare_events;
+    std::vector<tm_guard*> spare_guards;   // pinned guard staging buffers
     std::deque<Job> waiting;
-    std::vector<std::deque<Job>> running;  // per stream, in launch order
+    std::vector<std::deque<Batch>> running;  // per stream, in launch order
     size_t n_running = 0;
     std::deque<std::pair<uint64_t, tm_status>> finished;
     uint64_t next_id = 1;
@@ -134,88 +149,162 @@ struct tm_server {
 
 namespace {
 
-tm_status launch(tm_server* s, Job& j)
+tm_status launch(tm_server* s, Batch& b)
 {
-    hipStream_t st = s->streams[j.stream];
-    char* b = s->base + j.off;
-    uint64_t* du = reinterpret_cast<uint64_t*>(b + j.lay.u);
-    uint64_t* dv = reinterpret_cast<uint64_t*>(b + j.lay.v);
-    uint64_t* dw = reinterpret_cast<uint64_t*>(b + j.lay.w);
-    tm_guard* dg = reinterpret_cast<tm_guard*>(b + j.lay.g);
-    if (hipMemcpyAsync(du, j.req.u, j.lay.ub, hipMemcpyHostToDevice, st) != hipSuccess) return TM_ERR_HIP;
-    if (j.req.v == j.req.u) {
-        dv = du;  // squaring: one copy
-    } else if (hipMemcpyAsync(dv, j.req.v, j.lay.ub, hipMemcpyHostToDevice, st) != hipSuccess) {
-        return TM_ERR_HIP;
+    hipStream_t st = s->streams[b.stream];
+    const size_t k = b.jobs.size();
+    char* meta = s->base + b.meta_off;
+    tm_guard* dg = reinterpret_cast<tm_guard*>(meta + batch_guard_offset());
+    std::vector<tm_request> reqs(k);
+    std::vector<void*> wss(k);
+    std::vector<size_t> wsb(k);
+    std::vector<tm_guard*> gs(k);
+    for (size_t i = 0; i < k; i++) {
+        Job& j = b.jobs[i];
+        char* blk = s->base + j.off;
+        uint64_t* du = reinterpret_cast<uint64_t*>(blk + j.lay.u);
+        uint64_t* dv = reinterpret_cast<uint64_t*>(blk + j.lay.v);
+        if (hipMemcpyAsync(du, j.req.u, j.lay.ub, hipMemcpyHostToDevice, st) != hipSuccess) return TM_ERR_HIP;
+        if (j.req.v == j.req.u) {
+            dv = du;  // squaring: one copy
+        } else if (hipMemcpyAsync(dv, j.req.v, j.lay.ub, hipMemcpyHostToDevice, st) != hipSuccess) {
+            return TM_ERR_HIP;
+        }
+        reqs[i] = j.req;
+        reqs[i].u = du;
+        reqs[i].v = dv;
+        reqs[i].w = reinterpret_cast<uint64_t*>(blk + j.lay.w);
+        wss[i] = blk + j.lay.ws;
+        wsb[i] = j.lay.wsb;
+        gs[i] = dg + i;
     }
-    tm_status r = tm_mul((tm_kind)j.req.kind, dw, du, dv, j.req.n_bits, b + j.lay.ws, j.lay.wsb, st, dg);
+    tm_status r = k == 1 ? tm_mul((tm_kind)reqs[0].kind, reqs[0].w, reqs[0].u, reqs[0].v, reqs[0].n_bits,
+                                  wss[0], b.jobs[0].lay.wsb, st, gs[0])
+                         : tm_mul_packed(reqs.data(), k, wss.data(), wsb.data(), meta, batch_guard_offset(), st,
+                                         gs.data());
     if (r != TM_OK) return r;
-    if (hipMemcpyAsync(j.req.w, dw, j.lay.wb, hipMemcpyDeviceToHost, st) != hipSuccess) return TM_ERR_HIP;
-    if (j.guard_host &&
-        hipMemcpyAsync(j.guard_host, dg, sizeof(tm_guard), hipMemcpyDeviceToHost, st) != hipSuccess)
+    for (size_t i = 0; i < k; i++) {
+        Job& j = b.jobs[i];
+        if (hipMemcpyAsync(j.req.w, reqs[i].w, j.lay.wb, hipMemcpyDeviceToHost, st) != hipSuccess)
+            return TM_ERR_HIP;
+    }
+    if (s->spare_guards.empty()) {
+        void* h = nullptr;
+        if (hipHostMalloc(&h, kMaxBatch * sizeof(tm_guard), hipHostMallocDefault) != hipSuccess) return TM_ERR_HIP;
+        s->spare_guards.push_back(static_cast<tm_guard*>(h));
+    }
+    b.guards_host = s->spare_guards.back();
+    s->spare_guards.pop_back();
+    if (hipMemcpyAsync(b.guards_host, dg, k * sizeof(tm_guard), hipMemcpyDeviceToHost, st) != hipSuccess)
         return TM_ERR_HIP;
     if (s->spare_events.empty()) {
         hipEvent_t e;
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return TM_ERR_HIP;
         s->spare_events.push_back(e);
     }
-    j.done = s->spare_events.back();
+    b.done = s->spare_events.back();
     s->spare_events.pop_back();
-    if (hipEventRecord(j.done, st) != hipSuccess) return TM_ERR_HIP;
+    if (hipEventRecord(b.done, st) != hipSuccess) return TM_ERR_HIP;
     return TM_OK;
 }
 
-// Admit waiting requests in order while slots and memory allow (see the
-// header).
+void release_batch(tm_server* s, Batch& b)
+{
+    for (auto& j : b.jobs) s->pool.release(j.off, j.lay.total);
+    s->pool.release(b.meta_off, batch_block_bytes());
+    if (b.done) s->spare_events.push_back(b.done);
+    if (b.guards_host) s->spare_guards.push_back(b.guards_host);
+    b.done = nullptr;
+    b.guards_host = nullptr;
+}
+
+// Batches in flight per stream: one running and one queued behind it, so
+// requests that arrive meanwhile gather into the next batch.
+constexpr size_t kBatchesPerStream = 2;
+
+// The stream with the fewest batches in flight, or -1 if all are full.
+int free_stream(const tm_server* s)
+{
+    int best = -1;
+    for (int k = 0; k < (int)s->streams.size(); k++) {
+        if (s->running[k].size() >= kBatchesPerStream) continue;
+        if (best < 0 || s->running[k].size() < s->running[best].size() ||
+            (s->running[k].size() == s->running[best].size() && s->load[k] < s->load[best]))
+            best = k;
+    }
+    return best;
+}
+
+void start(tm_server* s, Batch& b)
+{
+    tm_status r = launch(s, b);
+    if (r != TM_OK) {
+        // the batch never reached the device or failed to launch: wait for
+        // whatever was queued on its stream, then release
+        (void)hipStreamSynchronize(s->streams[b.stream]);
+        for (auto& j : b.jobs) s->finished.emplace_back(j.id, r);
+        release_batch(s, b);
+        return;
+    }
+    s->load[b.stream] += (int)b.jobs.size();
+    s->n_running += b.jobs.size();
+    s->running[b.stream].push_back(std::move(b));
+}
+
+// Admit waiting requests in order while a stream has room for a batch and
+// memory allows (see the header), up to kMaxBatch requests per batch.
 void admit(tm_server* s)
 {
     size_t reserved = 0;
-    for (auto it = s->waiting.begin(); it != s->waiting.end() && s->n_running < s->max_inflight;) {
-        Job& j = *it;
-        size_t off;
-        const bool room = s->pool.free_bytes() >= reserved + j.lay.total;
-        if (room && s->pool.alloc(j.lay.total, off)) {
-            j.off = off;
-            int best = 0;
-            for (int k = 1; k < (int)s->streams.size(); k++)
-                if (s->load[k] < s->load[best]) best = k;
-            j.stream = best;
-            tm_status r = launch(s, j);
-            if (r != TM_OK) {
-                // the request never reached the device or failed to launch:
-                // wait for whatever was queued on its stream, then release
-                (void)hipStreamSynchronize(s->streams[best]);
-                s->pool.release(j.off, j.lay.total);
-                if (j.done) s->spare_events.push_back(j.done);
-                s->finished.emplace_back(j.id, r);
+    auto it = s->waiting.begin();
+    while (it != s->waiting.end() && s->n_running < s->max_inflight) {
+        const int st = free_stream(s);
+        if (st < 0) break;
+        Batch cur;
+        cur.stream = st;
+        if (s->pool.free_bytes() < reserved + batch_block_bytes() ||
+            !s->pool.alloc(batch_block_bytes(), cur.meta_off))
+            break;
+        while (it != s->waiting.end() && cur.jobs.size() < kMaxBatch &&
+               s->n_running + cur.jobs.size() < s->max_inflight) {
+            Job& j = *it;
+            size_t off;
+            const bool room = s->pool.free_bytes() >= reserved + j.lay.total;
+            if (room && s->pool.alloc(j.lay.total, off)) {
+                j.off = off;
+                cur.jobs.push_back(j);
+                it = s->waiting.erase(it);
             } else {
-                s->load[best]++;
-                s->running[best].push_back(j);
-                s->n_running++;
+                reserved += j.lay.total;
+                ++it;
             }
-            it = s->waiting.erase(it);
-        } else {
-            reserved += j.lay.total;
-            ++it;
         }
+        if (cur.jobs.empty()) {
+            s->pool.release(cur.meta_off, batch_block_bytes());
+            break;
+        }
+        start(s, cur);
     }
 }
 
-// Work on a stream completes in launch order, so only the oldest request of
+// Work on a stream completes in launch order, so only the oldest batch of
 // each stream needs an event query (or a wait, when block is set).
 void retire(tm_server* s, bool block)
 {
     for (auto& q : s->running) {
         while (!q.empty()) {
-            Job& j = q.front();
-            hipError_t e = block ? hipEventSynchronize(j.done) : hipEventQuery(j.done);
+            Batch& b = q.front();
+            hipError_t e = block ? hipEventSynchronize(b.done) : hipEventQuery(b.done);
             if (e == hipErrorNotReady) break;
-            s->finished.emplace_back(j.id, e == hipSuccess ? TM_OK : TM_ERR_HIP);
-            s->pool.release(j.off, j.lay.total);
-            s->load[j.stream]--;
-            s->spare_events.push_back(j.done);
+            for (size_t i = 0; i < b.jobs.size(); i++) {
+                const Job& j = b.jobs[i];
+                if (j.guard_host && e == hipSuccess) memcpy(j.guard_host, b.guards_host + i, sizeof(tm_guard));
+                s->finished.emplace_back(j.id, e == hipSuccess ? TM_OK : TM_ERR_HIP);
+            }
+            s->load[b.stream] -= (int)b.jobs.size();
+            s->n_running -= b.jobs.size();
+            release_batch(s, b);
             q.pop_front();
-            s->n_running--;
         }
     }
 }
@@ -237,7 +326,7 @@ tm_status tm_server_create(size_t pool_bytes, int n_streams, int max_inflight, t
     *out = nullptr;
     tm_server* s = new (std::nothrow) tm_server(align_up(pool_bytes));
     if (!s) return TM_ERR_INVALID;
-    s->max_inflight = max_inflight ? (size_t)max_inflight : (size_t)8 * n_streams;
+    s->max_inflight = max_inflight ? (size_t)max_inflight : kMaxBatch * kBatchesPerStream * n_streams;
     if (hipGetDevice(&s->dev) != hipSuccess || hipMalloc(&s->base, s->pool.size()) != hipSuccess) {
         delete s;
         return TM_ERR_HIP;
@@ -261,7 +350,7 @@ tm_status tm_server_submit(tm_server* s, const tm_request* req, tm_guard* guard_
     if (!s || !req || !req->u || !req->v || !req->w || req->kind > 2) return TM_ERR_INVALID;
     Job j;
     if (!layout_for((tm_kind)req->kind, req->n_bits, j.lay)) return TM_ERR_UNSUPPORTED;
-    if (j.lay.total > s->pool.size()) return TM_ERR_INVALID;  // can never be admitted
+    if (j.lay.total + batch_block_bytes() > s->pool.size()) return TM_ERR_INVALID;  // can never be admitted
     j.id = s->next_id++;
     j.req = *req;
     j.guard_host = guard_host;
@@ -306,10 +395,14 @@ void tm_server_destroy(tm_server* s)
 {
     if (!s) return;
     for (auto& q : s->running)
-        for (auto& j : q) (void)hipEventSynchronize(j.done);
+        for (auto& b : q) (void)hipEventSynchronize(b.done);
     for (auto& q : s->running)
-        for (auto& j : q) (void)hipEventDestroy(j.done);
+        for (auto& b : q) {
+            (void)hipEventDestroy(b.done);
+            (void)hipHostFree(b.guards_host);
+        }
     for (auto e : s->spare_events) (void)hipEventDestroy(e);
+    for (auto g : s->spare_guards) (void)hipHostFree(g);
     for (auto st : s->streams) (void)hipStreamDestroy(st);
     if (s->base) (void)hipFree(s->base);
     delete s;

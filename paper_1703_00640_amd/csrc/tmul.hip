@@ -2,6 +2,7 @@
 // Host code: planning, twiddle cache, template dispatch, launch sequence.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -194,6 +195,179 @@ bool launch_k1_any(int kind, const KParams& p, hipStream_t s)
     return launch_k1_hi(p.L1, p, s);
 }
 
+// ------------------------------------------------------------ packed launches
+//
+// Requests whose plans select the same kernel instance for a stage share one
+// launch of that instance; each workgroup finds its request in the group
+// table (see group_block).
+
+int mid_w(const KParams& p) { return (int)p.L2 < w_mid((int)p.Lm) ? (int)p.L2 : w_mid((int)p.Lm); }
+
+bool launch_k2g(uint32_t L2, const Group& g, uint32_t blocks, hipStream_t s)
+{
+    switch (L2) {
+#define X(V) \
+    case V: hipLaunchKernelGGL((k2_rows_pointwise_g<V>), dim3(blocks), dim3(NT2), 0, s, g); return true;
+        X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
+#undef X
+    }
+    return false;
+}
+
+template <bool INV>
+bool launch_midg(uint32_t Lm, int W, const Group& g, uint32_t blocks, hipStream_t s)
+{
+#define MIDW(LM, WW) \
+    if (Lm == LM && W == WW) { hipLaunchKernelGGL((k_mid_col_g<LM, WW, INV>), dim3(blocks), dim3(NTM), 0, s, g); return true; }
+#define MID(LM) MIDW(LM, 16) MIDW(LM, 32) MIDW(LM, 64)
+    MID(2) MID(4) MID(8) MID(16) MID(32) MID(64) MIDW(128, 16) MIDW(128, 32) MIDW(256, 16)
+#undef MID
+#undef MIDW
+    return false;
+}
+
+bool launch_k3g(uint32_t L1, const Group& g, uint32_t blocks, hipStream_t s)
+{
+    switch (L1) {
+#define X(V) \
+    case V: hipLaunchKernelGGL((k3_col_inverse_g<V, w3_for(V)>), dim3(blocks), dim3(NT3), 0, s, g); return true;
+        TM_L1_LIST(X)
+#undef X
+    }
+    return false;
+}
+
+void launch_k4g(int kind, int fb, const Group& g, uint32_t blocks, hipStream_t s)
+{
+    if (kind == TM_FULL) {
+        if (fb) hipLaunchKernelGGL((k4_backmap_carry_g<K_FULL, B_FULL>), dim3(blocks), dim3(NT4), 0, s, g);
+        else hipLaunchKernelGGL((k4_backmap_carry_g<K_FULL, 0>), dim3(blocks), dim3(NT4), 0, s, g);
+    } else if (kind == TM_LO) {
+        if (fb) hipLaunchKernelGGL((k4_backmap_carry_g<K_LO, B_TRUNC>), dim3(blocks), dim3(NT4), 0, s, g);
+        else hipLaunchKernelGGL((k4_backmap_carry_g<K_LO, 0>), dim3(blocks), dim3(NT4), 0, s, g);
+    } else {
+        if (fb) hipLaunchKernelGGL((k4_backmap_carry_g<K_HI, B_TRUNC>), dim3(blocks), dim3(NT4), 0, s, g);
+        else hipLaunchKernelGGL((k4_backmap_carry_g<K_HI, 0>), dim3(blocks), dim3(NT4), 0, s, g);
+    }
+}
+
+bool launch_k1g_any(int kind, uint32_t L1, int fb, const Group& g, uint32_t blocks, hipStream_t s)
+{
+    if (kind == TM_FULL) return launch_k1g_full(L1, fb, g, blocks, s);
+    if (kind == TM_LO) return launch_k1g_lo(L1, fb, g, blocks, s);
+    return launch_k1g_hi(L1, fb, g, blocks, s);
+}
+
+// Stages of one multiplication in launch order; the middle passes exist
+// only for three-pass splits.
+enum Stage { ST_K1, ST_MIDF, ST_K2, ST_MIDI, ST_K3, ST_K4, ST_COUNT };
+
+// Kernel instance (key) and grid of request p at stage st; false if the
+// request has no launch at that stage.
+bool stage_shape(int st, int kind, const KParams& p, uint64_t& key, uint32_t& nx, uint32_t& ny,
+                 uint32_t& nz)
+{
+    const int fb = fixed_b(kind, p) ? 1 : 0;
+    nx = ny = nz = 1;
+    switch (st) {
+    case ST_K1:
+        key = ((uint64_t)kind << 40) | ((uint64_t)fb << 32) | p.L1;
+        nx = p.R / (uint32_t)w1_for((int)p.L1);
+        ny = p.zb == p.za ? 1 : 2;
+        return true;
+    case ST_MIDF:
+    case ST_MIDI: {
+        if (p.Lm <= 1) return false;
+        const int W = mid_w(p);
+        key = ((uint64_t)p.Lm << 16) | (uint32_t)W;
+        nx = p.L2 / (uint32_t)W;
+        ny = p.L1;
+        nz = st == ST_MIDF && p.zb != p.za ? 2 : 1;
+        return true;
+    }
+    case ST_K2:
+        key = p.L2;
+        nx = k2_groups(p.L1, p.Lm);
+        return true;
+    case ST_K3:
+        key = p.L1;
+        nx = p.R / (uint32_t)w3_for((int)p.L1);
+        return true;
+    default:
+        key = ((uint64_t)kind << 1) | (uint64_t)fb;
+        nx = p.nstatus;
+        return true;
+    }
+}
+
+
+// Device metadata of a packed batch: parameters, then the group tables of
+// every stage (at most one entry per request and stage).
+size_t meta_params_bytes(size_t count) { return align256(count * sizeof(KParams)); }
+size_t meta_bytes_for(size_t count)
+{
+    return meta_params_bytes(count) + align256(count * ST_COUNT * sizeof(GroupEnt));
+}
+
+// Pinned host buffers for metadata uploads, per device.  A buffer is reused
+// once the event recorded after its upload has completed.
+struct StageBuf {
+    char* host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+std::mutex g_stage_mu;
+std::map<int, std::vector<StageBuf>> g_stage;
+constexpr size_t kStageBufs = 32;
+
+// Caller holds g_stage_mu.
+tm_status stage_acquire(int dev, size_t bytes, StageBuf*& out)
+{
+    auto& v = g_stage[dev];
+    for (auto& b : v) {
+        if (b.bytes < bytes) continue;
+        if (b.pending) {
+            hipError_t e = hipEventQuery(b.ev);
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess) return hip_fail(e, "hipEventQuery");
+            b.pending = false;
+        }
+        out = &b;
+        return TM_OK;
+    }
+    StageBuf* b;
+    if (v.size() < kStageBufs) {
+        v.emplace_back();
+        b = &v.back();
+        HIP_TRY(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
+    } else {
+        // every buffer busy or too small: wait for the first one
+        b = &v.front();
+        if (b->pending) HIP_TRY(hipEventSynchronize(b->ev));
+        b->pending = false;
+    }
+    if (b->bytes < bytes) {
+        if (b->host) HIP_TRY(hipHostFree(b->host));
+        b->host = nullptr;
+        b->bytes = 0;
+        const size_t nb = bytes < (64u << 10) ? (64u << 10) : bytes;
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&b->host), nb, hipHostMallocDefault));
+        b->bytes = nb;
+    }
+    out = b;
+    return TM_OK;
+}
+
+struct Launch {
+    int st;
+    int kind, fb;
+    uint32_t a, b;      // instance: K1/K3 L1, K2 L2, middle Lm and W
+    uint32_t ent0, nr;  // first table entry, requests
+    uint32_t blocks;
+};
+
+
 // ------------------------------------------------------------ params
 
 // Series constants.  c_r: alpha (-eps)^r/r!, gamma eps^r/r! (forward),
@@ -379,6 +553,126 @@ tm_status run(const Plan& P, uint64_t* w, const uint64_t* u, const uint64_t* v, 
     if (mode == DIAG_RUN) launch_k4<true>(P.kind, p, s);
     else launch_k4<false>(P.kind, p, s);
     if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
+    HIP_TRY(hipGetLastError());
+    return TM_OK;
+}
+
+tm_status run_packed(const tm_request* reqs, size_t count, void* const* ws, const size_t* ws_bytes,
+                     tm_guard* const* guards, void* meta, size_t meta_bytes, hipStream_t s)
+{
+    if (count == 0) return TM_OK;
+    if (!reqs || !ws || !ws_bytes || !meta) {
+        g_last_error = "null pointer";
+        return TM_ERR_INVALID;
+    }
+    if (meta_bytes < meta_bytes_for(count) || (reinterpret_cast<uintptr_t>(meta) & 255) != 0) {
+        g_last_error = "metadata area too small or not 256-byte aligned";
+        return TM_ERR_INVALID;
+    }
+    const size_t pbytes = meta_params_bytes(count);
+    std::vector<KParams> ps(count);
+    std::vector<int> kinds(count);
+    for (size_t i = 0; i < count; i++) {
+        const tm_request& r = reqs[i];
+        Plan P;
+        tm_status st = plan_for((tm_kind)r.kind, r.n_bits, P);
+        if (st != TM_OK) return st;
+        if (!r.u || !r.v || !r.w || !ws[i]) {
+            g_last_error = "null pointer";
+            return TM_ERR_INVALID;
+        }
+        if ((reinterpret_cast<uintptr_t>(ws[i]) & 255) != 0) {
+            g_last_error = "workspace must be 256-byte aligned";
+            return TM_ERR_INVALID;
+        }
+        if (ws_bytes[i] < P.ws_bytes) {
+            g_last_error = "workspace too small";
+            return TM_ERR_INVALID;
+        }
+        TwEntry tw;
+        st = get_twiddles(P.M, P.L1, P.Lm, P.L2, s, tw);
+        if (st != TM_OK) return st;
+        fill_params(P, r.u, r.v, r.w, ws[i], guards ? guards[i] : nullptr, tw, ps[i]);
+        kinds[i] = P.kind;
+    }
+    // group tables: per stage, requests sorted by kernel instance, at most
+    // GROUP_MAX per launch
+    std::vector<GroupEnt> ents;
+    std::vector<Launch> launches;
+    std::vector<std::pair<uint64_t, uint32_t>> order;
+    for (int st = 0; st < ST_COUNT; st++) {
+        order.clear();
+        for (size_t i = 0; i < count; i++) {
+            uint64_t key;
+            uint32_t nx, ny, nz;
+            if (stage_shape(st, kinds[i], ps[i], key, nx, ny, nz)) order.emplace_back(key, (uint32_t)i);
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [](const std::pair<uint64_t, uint32_t>& x, const std::pair<uint64_t, uint32_t>& y) {
+                             return x.first < y.first;
+                         });
+        for (size_t k = 0; k < order.size();) {
+            Launch L{};
+            L.st = st;
+            L.ent0 = (uint32_t)ents.size();
+            const uint64_t key = order[k].first;
+            const KParams& p0 = ps[order[k].second];
+            L.kind = kinds[order[k].second];
+            L.fb = fixed_b(L.kind, p0) ? 1 : 0;
+            L.a = st == ST_K2 ? p0.L2 : (st == ST_MIDF || st == ST_MIDI) ? p0.Lm : p0.L1;
+            L.b = (st == ST_MIDF || st == ST_MIDI) ? (uint32_t)mid_w(p0) : 0;
+            uint64_t blocks = 0;
+            while (k < order.size() && order[k].first == key && L.nr < (uint32_t)GROUP_MAX) {
+                const uint32_t i = order[k].second;
+                uint64_t kk;
+                uint32_t nx, ny, nz;
+                stage_shape(st, kinds[i], ps[i], kk, nx, ny, nz);
+                ents.push_back(GroupEnt{(uint32_t)blocks, nx, ny, i});
+                blocks += (uint64_t)nx * ny * nz;
+                L.nr++;
+                k++;
+            }
+            if (blocks >= 0xffffffffull) {
+                g_last_error = "packed launch too large";
+                return TM_ERR_UNSUPPORTED;
+            }
+            L.blocks = (uint32_t)blocks;
+            launches.push_back(L);
+        }
+    }
+    // one upload of parameters and tables through a pinned staging buffer
+    const size_t used = pbytes + ents.size() * sizeof(GroupEnt);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        StageBuf* sb = nullptr;
+        tm_status st = stage_acquire(dev, used, sb);
+        if (st != TM_OK) return st;
+        memcpy(sb->host, ps.data(), count * sizeof(KParams));
+        memcpy(sb->host + pbytes, ents.data(), ents.size() * sizeof(GroupEnt));
+        HIP_TRY(hipMemcpyAsync(meta, sb->host, used, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipEventRecord(sb->ev, s));
+        sb->pending = true;
+    }
+    const KParams* dps = static_cast<const KParams*>(meta);
+    const GroupEnt* dent = reinterpret_cast<const GroupEnt*>(static_cast<const char*>(meta) + pbytes);
+    for (const Launch& L : launches) {
+        const Group g{dps, dent + L.ent0, L.nr};
+        bool ok = true;
+        switch (L.st) {
+        case ST_K1: ok = launch_k1g_any(L.kind, L.a, L.fb, g, L.blocks, s); break;
+        case ST_MIDF: ok = launch_midg<false>(L.a, (int)L.b, g, L.blocks, s); break;
+        case ST_K2: ok = launch_k2g(L.a, g, L.blocks, s); break;
+        case ST_MIDI: ok = launch_midg<true>(L.a, (int)L.b, g, L.blocks, s); break;
+        case ST_K3: ok = launch_k3g(L.a, g, L.blocks, s); break;
+        default: launch_k4g(L.kind, L.fb, g, L.blocks, s); break;
+        }
+        if (!ok) {
+            g_last_error = "no packed kernel for a stage of the batch";
+            return TM_ERR_UNSUPPORTED;
+        }
+    }
     HIP_TRY(hipGetLastError());
     return TM_OK;
 }
@@ -604,30 +898,59 @@ tm_status tm_mul_hi(uint64_t* w, const uint64_t* u, const uint64_t* v, uint64_t 
 
 size_t tm_workspace_bytes_batched(const tm_request* reqs, size_t count)
 {
+    if (!reqs && count) return 0;
     size_t m = 0;
-    if (!reqs) return 0;
     for (size_t i = 0; i < count; i++) {
         size_t b = tm_workspace_bytes((tm_kind)reqs[i].kind, reqs[i].n_bits);
         if (b == 0) return 0;
-        if (b > m) m = b;
+        m += align256(b);
     }
-    return m;
+    return m + meta_bytes_for(count);
+}
+
+size_t tm_batch_meta_bytes(size_t count) { return meta_bytes_for(count); }
+
+tm_status tm_mul_packed(const tm_request* reqs, size_t count, void* const* workspaces,
+                        const size_t* workspace_bytes, void* meta, size_t meta_bytes,
+                        hipStream_t stream, tm_guard* const* guards_dev)
+{
+    return run_packed(reqs, count, workspaces, workspace_bytes, guards_dev, meta, meta_bytes, stream);
 }
 
 tm_status tm_mul_batched(const tm_request* reqs, size_t count, void* workspace,
                          size_t workspace_bytes, hipStream_t stream, tm_guard* guards_dev)
 {
-    if (!reqs && count) {
+    if (count == 0) return TM_OK;
+    if (!reqs || !workspace) {
         g_last_error = "null pointer";
         return TM_ERR_INVALID;
     }
-    for (size_t i = 0; i < count; i++) {
-        tm_status st = tm_mul((tm_kind)reqs[i].kind, reqs[i].w, reqs[i].u, reqs[i].v,
-                              reqs[i].n_bits, workspace, workspace_bytes, stream,
-                              guards_dev ? guards_dev + i : nullptr);
-        if (st != TM_OK) return st;
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) {
+        g_last_error = "workspace must be 256-byte aligned";
+        return TM_ERR_INVALID;
     }
-    return TM_OK;
+    const size_t need = tm_workspace_bytes_batched(reqs, count);
+    if (need == 0) {
+        g_last_error = "unsupported request in batch";
+        return TM_ERR_UNSUPPORTED;
+    }
+    if (workspace_bytes < need) {
+        g_last_error = "workspace too small";
+        return TM_ERR_INVALID;
+    }
+    // carve: one workspace per request, then the metadata area
+    std::vector<void*> ws(count);
+    std::vector<size_t> wsb(count);
+    std::vector<tm_guard*> gs(count);
+    char* base = static_cast<char*>(workspace);
+    size_t o = 0;
+    for (size_t i = 0; i < count; i++) {
+        ws[i] = base + o;
+        wsb[i] = tm_workspace_bytes((tm_kind)reqs[i].kind, reqs[i].n_bits);
+        o += align256(wsb[i]);
+        gs[i] = guards_dev ? guards_dev + i : nullptr;
+    }
+    return run_packed(reqs, count, ws.data(), wsb.data(), gs.data(), base + o, need - o, stream);
 }
 
 size_t tm_workspace_bytes_checked(tm_kind kind, uint64_t n_bits)
@@ -733,9 +1056,19 @@ const char* tm_last_error(void) { return g_last_error.c_str(); }
 
 void tm_release_caches(void)
 {
-    std::lock_guard<std::mutex> lk(g_tw_mu);
-    for (auto& kv : g_tw) (void)hipFree(kv.second.buf);
-    g_tw.clear();
+    {
+        std::lock_guard<std::mutex> lk(g_tw_mu);
+        for (auto& kv : g_tw) (void)hipFree(kv.second.buf);
+        g_tw.clear();
+    }
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    for (auto& kv : g_stage)
+        for (auto& b : kv.second) {
+            if (b.pending) (void)hipEventSynchronize(b.ev);
+            (void)hipEventDestroy(b.ev);
+            if (b.host) (void)hipHostFree(b.host);
+        }
+    g_stage.clear();
 }
 
 }  // extern "C"

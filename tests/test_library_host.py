@@ -107,6 +107,40 @@ def test_invalid_arguments_rejected_without_gpu():
     assert lib.tm_autotune(7, 4096, None, None) == 1
 
 
+def test_packed_batch_sizes_and_checks():
+    """Workspace of a packed batch = the requests' workspaces (256-byte
+    rounded) + the metadata area; malformed packed calls are rejected before
+    any device work."""
+    import paper_1703_00640_amd as tm
+    lib = tm._load()
+    mix = [("lo", 4096), ("hi", 100000), ("full", 777), ("lo", 1 << 20)]
+    reqs = (tm._Request * len(mix))()
+    for i, (k, n) in enumerate(mix):
+        reqs[i].kind = tm._kind(k)
+        reqs[i].n_bits = n
+    meta = lib.tm_batch_meta_bytes(len(mix))
+    assert meta > 0 and meta % 256 == 0
+    assert lib.tm_batch_meta_bytes(64) >= lib.tm_batch_meta_bytes(4)
+    want = sum((tm.workspace_bytes(k, n) + 255) // 256 * 256 for k, n in mix) + meta
+    assert lib.tm_workspace_bytes_batched(ctypes.byref(reqs), len(mix)) == want
+    reqs[1].kind = 9
+    assert lib.tm_workspace_bytes_batched(ctypes.byref(reqs), len(mix)) == 0
+    reqs[1].kind = 2
+    ws = (ctypes.c_void_p * len(mix))()
+    wsb = (ctypes.c_size_t * len(mix))()
+    # empty batch: nothing to do
+    assert lib.tm_mul_packed(None, 0, None, None, None, 0, None, None) == 0
+    assert lib.tm_mul_batched(None, 0, None, 0, None, None) == 0
+    # null metadata / workspace arrays, misaligned or short metadata area
+    assert lib.tm_mul_packed(ctypes.byref(reqs), len(mix), ws, wsb, None, meta, None, None) == 1
+    assert lib.tm_mul_packed(ctypes.byref(reqs), len(mix), None, wsb, 256, meta, None, None) == 1
+    assert lib.tm_mul_packed(ctypes.byref(reqs), len(mix), ws, wsb, 260, meta, None, None) == 1
+    assert lib.tm_mul_packed(ctypes.byref(reqs), len(mix), ws, wsb, 256, meta - 256, None, None) == 1
+    # a request with null operands
+    assert lib.tm_mul_packed(ctypes.byref(reqs), len(mix), ws, wsb, 256, meta, None, None) == 1
+    assert lib.tm_mul_batched(ctypes.byref(reqs), len(mix), None, 1 << 30, None, None) == 1
+
+
 def test_three_pass_split_for_large_n():
     """n = 2^30: M = L1 * Lm * L2 with a middle pass; n = 2^24 stays two-pass."""
     lo, full = _plan("lo", 1 << 30), _plan("full", 1 << 30)
