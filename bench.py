@@ -185,6 +185,60 @@ def serving_bench(count=4096, n_streams=4):
     return out
 
 
+def precision_bench(log2n=26, reps=5):
+    """The high product at n = 2^26 (the precision-comparison size): the
+    maximum rounding distance over all coefficients (the guard) and the time
+    for digit sizes b = 10..13 on uniform random operands and for the
+    default b on the adversarial digit pattern (every digit 2^(b-1)), and
+    whether the worst-case bound admits a plan at this size."""
+    import torch
+    import paper_1703_00640_amd as tm
+    from paper_1703_00640_amd import inputs
+    n = 1 << log2n
+    dev = torch.device("cuda:0")
+    u, v = inputs.operand_pair(n, 4)
+    du = torch.from_numpy(u.view(np.int64)).to(dev)
+    dv = torch.from_numpy(v.view(np.int64)).to(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def measure(a, b, guaranteed=False):
+        g = tm.new_guard(dev)
+        out = tm.mul("hi", a, b, n, guard=g, guaranteed=guaranteed)
+        torch.cuda.synchronize()
+        gd = tm.read_guard(g)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            tm.mul("hi", a, b, n, out=out, guaranteed=guaranteed)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return {"b": gd.b, "lam": gd.lam, "N": gd.N, "max_dist": round(gd.max_dist, 6),
+                "flags": gd.flags, "ms": round(e0.elapsed_time(e1) / reps, 4)}
+
+    res = {"n_bits": n, "kind": "hi", "fp64_random": []}
+    prev = os.environ.get("TM_FORCE_B")
+    try:
+        for b in (10, 11, 12, 13):
+            os.environ["TM_FORCE_B"] = str(b)
+            res["fp64_random"].append(measure(du, dv))
+    finally:
+        if prev is None:
+            os.environ.pop("TM_FORCE_B", None)
+        else:
+            os.environ["TM_FORCE_B"] = prev
+    b0 = tm.plan("hi", n)["b"]
+    adv = torch.from_numpy(inputs.digit_pattern(n, b0, 1 << (b0 - 1)).view(np.int64)).to(dev)
+    res["fp64_adversarial"] = measure(adv, adv)
+    try:
+        gp = tm.plan("hi", n, guaranteed=True)
+        res["fp64_guaranteed"] = measure(du, dv, guaranteed=True)
+        res["fp64_guaranteed"]["bound"] = gp["rounding_bound"]
+    except tm.TmulError as e:
+        res["fp64_guaranteed"] = {"supported": False, "reason": str(e)}
+    res["fp32_compensated"] = {"supported": False, "reason": "not built"}
+    return res
+
+
 def cpu_baseline(n_bits, threads):
     import oracle
     from paper_1703_00640_amd import inputs
@@ -207,6 +261,8 @@ def main():
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the mixed-request serving runs")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the rounding-distance comparison at n = 2^26")
     ap.add_argument("--large-log2n", type=int, default=30,
                     help="also time the three products at n = 2^this (0: skip)")
     ap.add_argument("--pmc-pass", action="store_true",
@@ -343,6 +399,8 @@ def main():
     torch.cuda.empty_cache()
     if args.large_log2n:
         result["large_n"] = large_n_bench(args.large_log2n, 5)
+    if not args.no_precision:
+        result["precision"] = precision_bench()
     if not args.no_serve:
         result["serving"] = serving_bench()
     if not args.no_cpu:

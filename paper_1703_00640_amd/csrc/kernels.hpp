@@ -661,30 +661,64 @@ __device__ __forceinline__ double2 pointwise_bin(double2 Ya, double2 Yam, double
 // k = k1 + L1 (km + Lm k2), k2 < L2, at positions ((k1 Lm + km) L2 + k2).
 // The mirror bin M - k lies in row (L1 - k1, Lm - 1 - km) at L2 - 1 - k2 when
 // k1 != 0, in row (0, Lm - km) at L2 - 1 - k2 when k1 = 0 and km != 0, and
-// row (0, 0) is its own mirror with k2 -> (L2 - k2) mod L2.  Workgroup g
-// takes the g-th row whose index does not exceed its mirror's.
+// row (0, 0) is its own mirror with k2 -> (L2 - k2) mod L2.  Besides (0, 0),
+// one more row is its own mirror: (0, Lm/2) for even Lm, else (L1/2,
+// (Lm-1)/2) for even L1 (none when both are odd).  Workgroup g < G-1 takes
+// the g-th row of a pair of distinct rows whose index does not exceed its
+// mirror's (A rows with 0 < k1 < L1/2, B with k1 = L1/2, C with k1 = 0);
+// the last workgroup takes both self-mirrored rows, so that no workgroup
+// loads a row twice.
+struct K2Rows {
+    uint32_t rowa, rowb;  // row indices k1 Lm + km of the two rows
+    uint32_t rhoa, rhob;  // their first bins k1 + L1 km
+    bool self;            // each row is its own mirror
+};
+
 __host__ __device__ inline uint32_t k2_groups(uint32_t L1, uint32_t Lm)
 {
     const uint32_t A = (L1 - 1) / 2 * Lm;
-    const uint32_t B = L1 % 2 == 0 ? (Lm + 1) / 2 : 0;
-    return A + B + Lm / 2 + 1;
+    const uint32_t B = L1 % 2 == 0 ? Lm / 2 : 0;
+    return A + B + (Lm - 1) / 2 + 1;
 }
 
-__device__ __forceinline__ void k2_rows_of(uint32_t g, uint32_t L1, uint32_t Lm, uint32_t& k1,
-                                           uint32_t& km)
+__device__ __forceinline__ K2Rows k2_rows_of(uint32_t g, uint32_t L1, uint32_t Lm)
 {
     const uint32_t A = (L1 - 1) / 2 * Lm;
-    const uint32_t B = L1 % 2 == 0 ? (Lm + 1) / 2 : 0;
-    if (g < A) {
-        k1 = 1 + g / Lm;
-        km = g % Lm;
-    } else if (g < A + B) {
-        k1 = L1 / 2;
-        km = g - A;
+    const uint32_t B = L1 % 2 == 0 ? Lm / 2 : 0;
+    const uint32_t C = (Lm - 1) / 2;
+    K2Rows r;
+    r.self = g >= A + B + C;
+    uint32_t k1, km, k1m, kmm;
+    if (r.self) {
+        k1 = km = 0;
+        if (Lm % 2 == 0) {
+            k1m = 0;
+            kmm = Lm / 2;
+        } else if (L1 % 2 == 0) {
+            k1m = L1 / 2;
+            kmm = (Lm - 1) / 2;
+        } else {
+            k1m = kmm = 0;
+        }
     } else {
-        k1 = 0;
-        km = g - A - B;
+        if (g < A) {
+            k1 = 1 + g / Lm;
+            km = g % Lm;
+        } else if (g < A + B) {
+            k1 = L1 / 2;
+            km = g - A;
+        } else {
+            k1 = 0;
+            km = 1 + (g - A - B);
+        }
+        k1m = k1 ? L1 - k1 : 0;
+        kmm = k1 ? Lm - 1 - km : Lm - km;
     }
+    r.rowa = k1 * Lm + km;
+    r.rowb = k1m * Lm + kmm;
+    r.rhoa = k1 + L1 * km;
+    r.rhob = k1m + L1 * kmm;
+    return r;
 }
 
 template <int L2>
@@ -694,16 +728,12 @@ __device__ __forceinline__ void k2_body(const KParams& p, const Blk bk)
     __shared__ double2 rows[padded(4 * L2)];
     __shared__ double2 twl[twl_size(L2)];
     const uint32_t L1 = p.L1, Lm = p.Lm;
-    uint32_t k1, km;
-    k2_rows_of(bk.x, L1, Lm, k1, km);
-    const uint32_t k1m = k1 ? L1 - k1 : 0;
-    const uint32_t kmm = k1 ? Lm - 1 - km : (km ? Lm - km : 0);
-    const uint32_t rowa = k1 * Lm + km, rowb = k1m * Lm + kmm;
-    const bool zero_row = k1 == 0 && km == 0;
+    const K2Rows rr = k2_rows_of(bk.x, L1, Lm);
+    const uint32_t rowa = rr.rowa, rowb = rr.rowb;
     load_twl<L2, NT2>(twl, p.tw2);
     // exp(-2 pi i k / M) for bin k = rho + L1 Lm k2 (rho = k1 + L1 km) is
     // exp(-2 pi i rho / M) times exp(-2 pi i k2 / L2): one table value per row
-    const uint32_t rhoa = k1 + L1 * km, rhob = k1m + L1 * kmm;
+    const uint32_t rhoa = rr.rhoa, rhob = rr.rhob;
     const double2 wr0a = p.tw.lo[rhoa & p.tw.mask], wr0b = p.tw.hi[rhoa >> p.tw.shift];
     const double2 wr1a = p.tw.lo[rhob & p.tw.mask], wr1b = p.tw.hi[rhob >> p.tw.shift];
     {
@@ -736,8 +766,10 @@ __device__ __forceinline__ void k2_body(const KParams& p, const Blk bk)
         const int e = threadIdx.x + t * NT2;
         if (e < 2 * L2) {
             const int pr = e / L2, k2 = e % L2;
-            const int mk2 = zero_row ? (L2 - k2) % L2 : L2 - 1 - k2;
-            const int mr = 1 - pr;
+            // self-mirrored rows pair with themselves (row (0, 0) in slot 0
+            // with k2 -> (L2 - k2) mod L2), distinct rows with each other
+            const int mk2 = rr.self && pr == 0 ? (L2 - k2) % L2 : L2 - 1 - k2;
+            const int mr = rr.self ? pr : 1 - pr;
             qv[t] = pointwise_bin(rows[pidx((2 * pr) * L2 + k2)], rows[pidx((2 * mr) * L2 + mk2)],
                                   rows[pidx((2 * pr + 1) * L2 + k2)], rows[pidx((2 * mr + 1) * L2 + mk2)],
                                   cmul(pr ? wrow1 : wrow0, tw_half<L2>(twl, k2)));
