@@ -163,6 +163,7 @@ def serving_bench(count=4096, n_streams=4):
     memory (copies in and out are part of every request).  First all
     requests at t = 0 (saturation throughput R), then Poisson arrivals at
     0.5 R and 0.9 R; latency = completion seen on the host - arrival."""
+    import paper_1703_00640_amd as tm
     from paper_1703_00640_amd import inputs, serving
     mix = inputs.serving_mix(count, seed=6)
     m = serving.Mix(mix, seed=7)
@@ -177,12 +178,70 @@ def serving_bench(count=4096, n_streams=4):
         st, _, _ = serving.run(m, arr, n_streams=n_streams)
         st["offered_rps"] = rate
         out["poisson_%.1f" % frac] = st
+    # storage: the truncated products' transforms hold N = 3n/b' reals
+    # against 2N for the full product; admission capacity of a 1 GiB pool
+    cap = {}
+    for lg in (16, 22, 26):
+        nb = 1 << lg
+        row = {}
+        for k in ("lo", "hi", "full"):
+            fp = tm.server_footprint(k, nb)
+            row[k] = {"workspace_bytes": tm.workspace_bytes(k, nb), "footprint_bytes": fp,
+                      "per_gib": (1 << 30) // fp if fp else 0}
+        row["lo_full_workspace_ratio"] = round(row["lo"]["workspace_bytes"] / row["full"]["workspace_bytes"], 4)
+        cap["n=2^%d" % lg] = row
+    out["admission_capacity"] = cap
     for v in out.values():
         if isinstance(v, dict):
             for k in list(v):
                 if isinstance(v[k], float):
                     v[k] = round(v[k], 6)
     return out
+
+
+def small_latency_bench(log2n=16, reps=200):
+    """One small multiplication at a time (n = 2^16, the smallest benchmark
+    size): microseconds per call for back-to-back eager calls (launch-bound
+    at this size) and for replays of the same call captured in a HIP graph."""
+    import torch
+    import paper_1703_00640_amd as tm
+    from paper_1703_00640_amd import inputs
+    n = 1 << log2n
+    L = n // 64
+    dev = torch.device("cuda:0")
+    u, v = inputs.operand_pair(n, 2)
+    du = torch.from_numpy(u.view(np.int64)).to(dev)
+    dv = torch.from_numpy(v.view(np.int64)).to(dev)
+    res = {"n_bits": n, "eager_us": {}, "graph_us": {}}
+    for k in ("lo", "hi", "full"):
+        tm.prepare(k, n)
+        out = torch.empty(2 * L if k == "full" else L, dtype=torch.int64, device=dev)
+        ws = torch.empty(tm.plan(k, n)["workspace_bytes"], dtype=torch.uint8, device=dev)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(3):
+                tm.mul(k, du, dv, n, out=out, workspace=ws)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            tm.mul(k, du, dv, n, out=out, workspace=ws)
+        stream = torch.cuda.current_stream(dev)
+        for name, fn in (("eager_us", lambda: tm.mul(k, du, dv, n, out=out, workspace=ws)),
+                         ("graph_us", graph.replay)):
+            for _ in range(5):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            res[name][k] = round(e0.elapsed_time(e1) * 1e3 / reps, 2)
+        del graph
+    return res
 
 
 def precision_bench(log2n=26, reps=5):
@@ -401,6 +460,7 @@ def main():
         result["large_n"] = large_n_bench(args.large_log2n, 5)
     if not args.no_precision:
         result["precision"] = precision_bench()
+        result["small_n"] = small_latency_bench()
     if not args.no_serve:
         result["serving"] = serving_bench()
     if not args.no_cpu:

@@ -26,6 +26,12 @@
  * - Errors are reported through the return code only; nothing is thrown and
  *   nothing exits.  After TM_ERR_HIP, tm_last_error() describes the failing
  *   HIP call (per thread).
+ * - Graph capture: tm_mul and its wrappers launch kernels only, so they can
+ *   be captured into a HIP graph (stream capture) once the size's tables
+ *   exist (tm_prepare, or one earlier call); a call that would have to
+ *   build them during a capture returns TM_ERR_INVALID.  Replays read the
+ *   captured buffers' current contents.  tm_mul_batched / tm_mul_packed
+ *   upload metadata from a reused host buffer and are not for capture.
  * - The library keeps one device-side cache per (device, transform length):
  *   the FFT twiddle tables, built on first use (this first call synchronises
  *   its stream once), and a few pinned host buffers for the launch metadata

@@ -103,6 +103,14 @@ tm_status get_twiddles(uint64_t M, uint32_t L1, uint32_t Lm, uint32_t L2, hipStr
         out = it->second;
         return TM_OK;
     }
+    // building a table allocates and synchronises: not allowed while the
+    // stream is being captured into a graph (tm_prepare the size first)
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) {
+        g_last_error = "twiddle tables for this size are not built: call tm_prepare before capturing";
+        return TM_ERR_INVALID;
+    }
     uint32_t sh = (uint32_t)((lg_ceil(M) + 1) / 2);
     uint32_t S = 1u << sh;
     uint32_t nhi = (uint32_t)((M + S - 1) / S);

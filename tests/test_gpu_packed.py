@@ -133,3 +133,55 @@ def test_packed_single_empty_and_tiny():
     check_batch(run_batch([("full", 12345)], seed=900))
     check_batch(run_batch([("hi", 1), ("lo", 65), ("full", 1), ("lo", 1 << 14), ("hi", 64),
                            ("hi", 1 << 15)], seed=950))
+
+
+def test_graph_capture_replays_match_eager():
+    """tm_mul captured into a HIP graph (torch stream capture) after
+    tm_prepare: every replay, with new operands copied in eagerly between
+    replays, equals an eager call and the oracle.  A size whose tables do
+    not exist yet is refused inside the capture, before any launch."""
+    tm = _tm()
+    for kind, n in (("lo", 1 << 16), ("hi", 100003), ("full", 70000)):
+        say("[graph] %s n=%d" % (kind, n))
+        tm.prepare(kind, n)
+        L = inputs.nlimbs(n)
+        du = torch.zeros(L, dtype=torch.int64, device=dev())
+        dv = torch.zeros(L, dtype=torch.int64, device=dev())
+        out = torch.zeros(2 * L if kind == "full" else L, dtype=torch.int64, device=dev())
+        ws = torch.empty(tm.plan(kind, n)["workspace_bytes"], dtype=torch.uint8, device=dev())
+        gbuf = tm.new_guard(dev())
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            tm.mul(kind, du, dv, n, out=out, workspace=ws, guard=gbuf)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            tm.mul(kind, du, dv, n, out=out, workspace=ws, guard=gbuf)
+        for rep in range(3):
+            u, v = inputs.operand_pair(n, 1200 + rep)
+            du.copy_(to_dev(u))
+            dv.copy_(to_dev(v))
+            graph.replay()
+            torch.cuda.synchronize()
+            w = to_host(out)
+            g = tm.read_guard(gbuf)
+            w1, g1 = alone(kind, to_dev(u), to_dev(v), n)
+            assert np.array_equal(w, w1), (kind, n, rep)
+            assert g.as_dict() == g1.as_dict(), (kind, n, rep)
+            check_oracle(kind, u, v, n, w)
+        del graph
+    # a size whose transform length no earlier test uses (M = 2^19): its
+    # tables cannot be built inside a capture
+    n = 9000000
+    L = inputs.nlimbs(n)
+    du = torch.zeros(L, dtype=torch.int64, device=dev())
+    out = torch.zeros(L, dtype=torch.int64, device=dev())
+    ws = torch.empty(tm.plan("lo", n)["workspace_bytes"], dtype=torch.uint8, device=dev())
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        with pytest.raises(tm.TmulError):
+            tm.mul("lo", du, du, n, out=out, workspace=ws)
+    torch.cuda.synchronize()
