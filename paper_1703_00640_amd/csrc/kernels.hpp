@@ -245,11 +245,29 @@ __device__ __forceinline__ double coef_back(const KParams& p, uint32_t k, int r)
     return v;
 }
 
-// Clear the per-call state that K4 accumulates into (output limbs for the
-// partial-limb OR, guard, look-back records, ticket).  Done by K1.
+// Clear the per-call state that K4 accumulates into (guard, look-back
+// records, ticket, and the output limbs K4 ORs into).  Done by K1.
+// K4 workgroup g owns limbs [g LPW, (g+1) LPW) of S (LPW = DPW b / 64) and
+// writes output limb i (bits [64 i + off, 64 i + off + 64) of S) with a
+// plain store when those bits lie in its own limbs.  Only three kinds of
+// output limb are OR-ed and need a zero start: one that straddles two
+// workgroups (off not a multiple of 64 and S limb i + off/64 + 1 a
+// multiple of LPW), the last limb when it is partial, and any limb beyond
+// the workgroups' limbs.
 __device__ __forceinline__ void clear_state(const KParams& p, uint32_t gid, uint32_t gsize)
 {
-    for (uint64_t i = gid; i < p.out_limbs; i += gsize) p.w[i] = 0;
+    const uint64_t lpw = (uint64_t)(DPW / 64) * (uint64_t)p.b;
+    const uint64_t q = p.off >> 6;
+    if (p.off & 63) {
+        for (uint64_t j = 1 + gid; j <= p.nstatus; j += gsize) {
+            const uint64_t s1 = j * lpw;  // S limb above the boundary
+            if (s1 >= q + 1 && s1 - q - 1 < p.out_limbs) p.w[s1 - q - 1] = 0;
+        }
+    }
+    const uint64_t covered = (uint64_t)p.nstatus * lpw;  // S limbs written by K4
+    const uint64_t first_out = covered > q + 1 ? covered - q - 1 : 0;
+    for (uint64_t i = first_out + gid; i < p.out_limbs; i += gsize) p.w[i] = 0;
+    if (gid == 0 && (p.out_bits & 63) && p.out_limbs) p.w[p.out_limbs - 1] = 0;
     for (uint64_t i = gid; i < 2ull * p.nstatus; i += gsize) p.status[i] = 0;
     if (gid == 0) {
         *p.ticket = 0;
