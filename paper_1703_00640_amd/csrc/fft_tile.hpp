@@ -227,21 +227,25 @@ constexpr int pick_radix(int rem)
     return rem % 3 == 0 ? 3 : rem % 5 == 0 ? 5 : rem % 16 == 0 ? 16 : rem % 8 == 0 ? 8 : rem % 4 == 0 ? 4 : 2;
 }
 
-// LDS tiles are padded by one element after every 16, which spreads the
-// power-of-two strides of the Stockham stages over the LDS banks.
+// LDS tiles are padded by one element after every 2^PS (16 by default),
+// which spreads the power-of-two strides of the Stockham stages over the
+// LDS banks.
 #ifndef TM_PAD_SHIFT
 #define TM_PAD_SHIFT 4
 #endif
-__device__ __forceinline__ int pidx(int e) { return TM_PAD_SHIFT ? e + (e >> TM_PAD_SHIFT) : e; }
-constexpr int padded(int n) { return TM_PAD_SHIFT ? n + (n >> TM_PAD_SHIFT) + 1 : n; }
+// (PS: log2 of the elements between pads, 0 for none; per kernel)
+template <int PS = TM_PAD_SHIFT>
+__device__ __forceinline__ int pidx(int e) { return PS ? e + (e >> PS) : e; }
+template <int PS = TM_PAD_SHIFT>
+constexpr int padded(int n) { return PS ? n + (n >> PS) + 1 : n; }
 
 // Element (j, c) of the tile: sequence c, position j.
 //   COLS: sequences interleaved (index j*NB + c)  - column tiles
 //   rows: sequences contiguous  (index c*RS + j)   - row tiles
-template <bool COLS, int NB, int RS>
+template <bool COLS, int NB, int RS, int PS>
 __device__ __forceinline__ int tile_addr(int j, int c)
 {
-    return pidx(COLS ? j * NB + c : c * RS + j);
+    return pidx<PS>(COLS ? j * NB + c : c * RS + j);
 }
 
 // LDS twiddle table length for a sub-transform of length P, and lookup of
@@ -259,7 +263,7 @@ __device__ __forceinline__ double2 tw_half(const double2* twl, int e)
 }
 
 // One Stockham stage of radix R after NS points have been combined.
-template <int P, int R, int NS, int NB, int NT, bool INV, bool COLS, int RS>
+template <int P, int R, int NS, int NB, int NT, bool INV, bool COLS, int RS, int PS>
 __device__ __forceinline__ void fft_stage(double2* buf, const double2* twl)
 {
     constexpr int BF = P / R;
@@ -276,7 +280,7 @@ __device__ __forceinline__ void fft_stage(double2* buf, const double2* twl)
         cc[q] = COLS ? idx % NB : idx / BF;
         if (TOT % NT == 0 || idx < TOT) {
 #pragma unroll
-            for (int r = 0; r < R; r++) v[q][r] = buf[tile_addr<COLS, NB, RS>(jj[q] + r * BF, cc[q])];
+            for (int r = 0; r < R; r++) v[q][r] = buf[tile_addr<COLS, NB, RS, PS>(jj[q] + r * BF, cc[q])];
         }
     }
     __syncthreads();
@@ -297,29 +301,29 @@ __device__ __forceinline__ void fft_stage(double2* buf, const double2* twl)
             dftR<R, INV>(v[q]);
             const int out = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; r++) buf[tile_addr<COLS, NB, RS>(out + r * NS, cc[q])] = v[q][r];
+            for (int r = 0; r < R; r++) buf[tile_addr<COLS, NB, RS, PS>(out + r * NS, cc[q])] = v[q][r];
         }
     }
     __syncthreads();
 }
 
-template <int P, int NS, int NB, int NT, bool INV, bool COLS, int RS>
+template <int P, int NS, int NB, int NT, bool INV, bool COLS, int RS, int PS>
 __device__ __forceinline__ void fft_stages(double2* buf, const double2* twl)
 {
     if constexpr (NS < P) {
         constexpr int R = pick_radix(P / NS);
-        fft_stage<P, R, NS, NB, NT, INV, COLS, RS>(buf, twl);
-        fft_stages<P, NS * R, NB, NT, INV, COLS, RS>(buf, twl);
+        fft_stage<P, R, NS, NB, NT, INV, COLS, RS, PS>(buf, twl);
+        fft_stages<P, NS * R, NB, NT, INV, COLS, RS, PS>(buf, twl);
     }
 }
 
 // In-place DFT of NB sequences of length P in LDS; twl is an LDS table of
 // exp(-2 pi i e / P), e < P.  Caller must __syncthreads() before (data and
 // table written); the routine ends with a barrier.
-template <int P, int NB, int NT, bool INV, bool COLS, int RS = P>
+template <int P, int NB, int NT, bool INV, bool COLS, int RS = P, int PS = TM_PAD_SHIFT>
 __device__ __forceinline__ void tile_fft(double2* buf, const double2* twl)
 {
-    fft_stages<P, 1, NB, NT, INV, COLS, RS>(buf, twl);
+    fft_stages<P, 1, NB, NT, INV, COLS, RS, PS>(buf, twl);
 }
 
 // Copy the sub-transform table into LDS: the first half only when P is even

@@ -23,7 +23,8 @@
 // Build-time knobs (defaults are the measured best on MI355X): TM_NT1,
 // TM_NT2, TM_NT3, TM_NT4, TM_NTM threads per workgroup of K1, K2, K3, K4 and
 // the middle pass; TM_TILE1 / TM_TILE3 complex elements per K1 / K3 column
-// tile; TM_DPT coefficients per K4 thread; TM_PAD_SHIFT LDS tile padding.
+// tile; TM_DPT coefficients per K4 thread; TM_PAD_SHIFT LDS tile padding
+// (TM_PAD_K2 for K2's row tiles).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -47,6 +48,10 @@ constexpr int LMAX = 9;         // largest supported series length lambda
 #ifndef TM_NT4
 #define TM_NT4 512
 #endif
+#ifndef TM_PAD_K2
+#define TM_PAD_K2 5
+#endif
+constexpr int PAD2 = TM_PAD_K2;  // K2 row tiles: one pad element per 32 (measured best)
 #ifndef TM_NT3
 #define TM_NT3 256
 #endif
@@ -743,7 +748,7 @@ template <int L2>
 __device__ __forceinline__ void k2_body(const KParams& p, const Blk bk)
 {
     // rows 0,1: operands u,v at row (k1, km); rows 2,3: at the mirror row
-    __shared__ double2 rows[padded(4 * L2)];
+    __shared__ double2 rows[padded<PAD2>(4 * L2)];
     __shared__ double2 twl[twl_size(L2)];
     const uint32_t L1 = p.L1, Lm = p.Lm;
     const K2Rows rr = k2_rows_of(bk.x, L1, Lm);
@@ -770,11 +775,11 @@ __device__ __forceinline__ void k2_body(const KParams& p, const Blk bk)
 #pragma unroll
         for (int q = 0; q < PL; q++) {
             const int e = threadIdx.x + q * NT2;
-            if (4 * L2 % NT2 == 0 || e < 4 * L2) rows[pidx(e)] = v[q];
+            if (4 * L2 % NT2 == 0 || e < 4 * L2) rows[pidx<PAD2>(e)] = v[q];
         }
     }
     __syncthreads();
-    tile_fft<L2, 4, NT2, false, false, L2>(rows, twl);
+    tile_fft<L2, 4, NT2, false, false, L2, PAD2>(rows, twl);
 
     constexpr int PER = (2 * L2 + NT2 - 1) / NT2;
     const double2 wrow0 = cmul(wr0a, wr0b), wrow1 = cmul(wr1a, wr1b);
@@ -788,8 +793,8 @@ __device__ __forceinline__ void k2_body(const KParams& p, const Blk bk)
             // with k2 -> (L2 - k2) mod L2), distinct rows with each other
             const int mk2 = rr.self && pr == 0 ? (L2 - k2) % L2 : L2 - 1 - k2;
             const int mr = rr.self ? pr : 1 - pr;
-            qv[t] = pointwise_bin(rows[pidx((2 * pr) * L2 + k2)], rows[pidx((2 * mr) * L2 + mk2)],
-                                  rows[pidx((2 * pr + 1) * L2 + k2)], rows[pidx((2 * mr + 1) * L2 + mk2)],
+            qv[t] = pointwise_bin(rows[pidx<PAD2>((2 * pr) * L2 + k2)], rows[pidx<PAD2>((2 * mr) * L2 + mk2)],
+                                  rows[pidx<PAD2>((2 * pr + 1) * L2 + k2)], rows[pidx<PAD2>((2 * mr + 1) * L2 + mk2)],
                                   cmul(pr ? wrow1 : wrow0, tw_half<L2>(twl, k2)));
         }
     }
@@ -799,16 +804,16 @@ __device__ __forceinline__ void k2_body(const KParams& p, const Blk bk)
         const int e = threadIdx.x + t * NT2;
         if (e < 2 * L2) {
             const int pr = e / L2, k2 = e % L2;
-            rows[pidx((2 * pr) * L2 + k2)] = qv[t];
+            rows[pidx<PAD2>((2 * pr) * L2 + k2)] = qv[t];
         }
     }
     __syncthreads();
     // inverse row DFTs of rows 0 and 2 (row stride 2*L2)
-    tile_fft<L2, 2, NT2, true, false, 2 * L2>(rows, twl);
+    tile_fft<L2, 2, NT2, true, false, 2 * L2, PAD2>(rows, twl);
     for (int e = threadIdx.x; e < 2 * L2; e += NT2) {
         const int pr = e / L2, j2 = e % L2;
         if (pr == 1 && rowb == rowa) continue;
-        p.za[(size_t)(pr ? rowb : rowa) * L2 + j2] = rows[pidx((2 * pr) * L2 + j2)];
+        p.za[(size_t)(pr ? rowb : rowa) * L2 + j2] = rows[pidx<PAD2>((2 * pr) * L2 + j2)];
     }
 }
 
@@ -1451,14 +1456,17 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
     }
 }
 
+// eight waves per SIMD (four workgroups per CU, as the LDS allows): the
+// register bound this sets makes the high and full products' K4 about 12%
+// faster at n = 2^30
 template <int KIND, bool DIAG, int B>
-__global__ __launch_bounds__(NT4) void k4_backmap_carry(KParams p)
+__global__ __launch_bounds__(NT4, 8) void k4_backmap_carry(KParams p)
 {
     k4_body<KIND, DIAG, B>(p, blk_hw());
 }
 
 template <int KIND, int B>
-__global__ __launch_bounds__(NT4) void k4_backmap_carry_g(Group g)
+__global__ __launch_bounds__(NT4, 8) void k4_backmap_carry_g(Group g)
 {
     uint32_t pi;
     const Blk bk = group_block(g, pi);
