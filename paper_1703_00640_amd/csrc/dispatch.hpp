@@ -23,7 +23,8 @@ constexpr int w3_for(int L1) { return w_for(L1, TILE3); }
 
 #define TM_L1_LIST(X) \
     X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) \
-    X(256) X(384) X(512) X(768) X(1024) X(5) X(10) X(20) X(40) X(80) X(160) X(320) X(640)
+    X(256) X(384) X(512) X(768) X(1024) X(5) X(10) X(20) X(40) X(80) X(160) X(320) X(640) \
+    X(7) X(14) X(28) X(56) X(112) X(224) X(448) X(896)
 
 // Compile-time digit size of the K1 / K4 instances for a plan: the default
 // sizes (b = 11 truncated with lam <= LB_FIXED, b = 16 full) have their own

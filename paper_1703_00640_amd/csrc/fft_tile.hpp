@@ -2,7 +2,7 @@
 //
 // This is the building block of the Convolution step (Section 2.1: real
 // FFTs, pointwise product, inverse FFT).  A tile holds NB independent
-// sequences of length P; a Stockham autosort schedule of radix-3/5/16/8/4/2
+// sequences of length P; a Stockham autosort schedule of radix-3/5/7/16/8/4/2
 // stages transforms all of them in place, one LDS round trip per stage
 // (radix 16 runs as 4 x 4 in registers).  Each butterfly reads one stage
 // twiddle from an LDS copy of exp(-2 pi i e / P) and forms the others as
@@ -113,6 +113,44 @@ __device__ __forceinline__ void dft5(double2* v)
     v[3] = csub(a2, b2);
 }
 
+// 7-point DFT from the symmetric sums a_k = v_k + v_(7-k) and differences
+// d_k = v_k - v_(7-k), k = 1..3: X_m = v_0 + sum_k a_k cos(2 pi k m / 7)
+// -+ i sum_k d_k sin(2 pi k m / 7), and X_(7-m) with the opposite sign of
+// the sine part (forward: minus).
+template <bool INV>
+__device__ __forceinline__ void dft7(double2* v)
+{
+    const double c1 = 0.62348980185873353053, c2 = -0.22252093395631440429;
+    const double c3 = -0.90096886790241912624;
+    const double s1 = 0.78183148246802980871, s2 = 0.97492791218182360702;
+    const double s3 = 0.43388373911755812048;
+    const double2 a1 = cadd(v[1], v[6]), a2 = cadd(v[2], v[5]), a3 = cadd(v[3], v[4]);
+    const double2 d1 = csub(v[1], v[6]), d2 = csub(v[2], v[5]), d3 = csub(v[3], v[4]);
+    const double2 x0 = v[0];
+    // cosine parts: rows (c1 c2 c3), (c2 c3 c1), (c3 c1 c2)
+    const double2 r1 = make_double2(fma(c3, a3.x, fma(c2, a2.x, fma(c1, a1.x, x0.x))),
+                                    fma(c3, a3.y, fma(c2, a2.y, fma(c1, a1.y, x0.y))));
+    const double2 r2 = make_double2(fma(c1, a3.x, fma(c3, a2.x, fma(c2, a1.x, x0.x))),
+                                    fma(c1, a3.y, fma(c3, a2.y, fma(c2, a1.y, x0.y))));
+    const double2 r3 = make_double2(fma(c2, a3.x, fma(c1, a2.x, fma(c3, a1.x, x0.x))),
+                                    fma(c2, a3.y, fma(c1, a2.y, fma(c3, a1.y, x0.y))));
+    // sine parts: rows (s1 s2 s3), (s2 -s3 -s1), (s3 -s1 s2), times -i
+    // (forward) or +i (inverse)
+    const double2 i1 = mul_mi<INV>(make_double2(fma(s3, d3.x, fma(s2, d2.x, s1 * d1.x)),
+                                                fma(s3, d3.y, fma(s2, d2.y, s1 * d1.y))));
+    const double2 i2 = mul_mi<INV>(make_double2(fma(-s1, d3.x, fma(-s3, d2.x, s2 * d1.x)),
+                                                fma(-s1, d3.y, fma(-s3, d2.y, s2 * d1.y))));
+    const double2 i3 = mul_mi<INV>(make_double2(fma(s2, d3.x, fma(-s1, d2.x, s3 * d1.x)),
+                                                fma(s2, d3.y, fma(-s1, d2.y, s3 * d1.y))));
+    v[0] = cadd(x0, cadd(a1, cadd(a2, a3)));
+    v[1] = cadd(r1, i1);
+    v[6] = csub(r1, i1);
+    v[2] = cadd(r2, i2);
+    v[5] = csub(r2, i2);
+    v[3] = cadd(r3, i3);
+    v[4] = csub(r3, i3);
+}
+
 template <bool INV>
 __device__ __forceinline__ void dft4(double2* v)
 {
@@ -207,6 +245,7 @@ __device__ __forceinline__ void dftR(double2* v)
     else if constexpr (R == 3) dft3<INV>(v);
     else if constexpr (R == 4) dft4<INV>(v);
     else if constexpr (R == 5) dft5<INV>(v);
+    else if constexpr (R == 7) dft7<INV>(v);
     else if constexpr (R == 8) dft8<INV>(v);
     else dft16<INV>(v);
 }
@@ -224,7 +263,13 @@ __device__ __forceinline__ void tw_powers(double2 w, double2* pw)
 // radix of the next stage given the remaining length
 constexpr int pick_radix(int rem)
 {
-    return rem % 3 == 0 ? 3 : rem % 5 == 0 ? 5 : rem % 16 == 0 ? 16 : rem % 8 == 0 ? 8 : rem % 4 == 0 ? 4 : 2;
+    return rem % 3 == 0   ? 3
+           : rem % 5 == 0 ? 5
+           : rem % 7 == 0 ? 7
+           : rem % 16 == 0 ? 16
+           : rem % 8 == 0 ? 8
+           : rem % 4 == 0 ? 4
+                          : 2;
 }
 
 // LDS tiles are padded by one element after every 2^PS (16 by default),

@@ -5,7 +5,7 @@
 //   full: N_digits b >= n, convolution length 2 N_digits;
 //   low:  b >= 4, N >= 3, N b >= n;
 //   high: b >= 4, N >= 3, (N + 1) b >= n + lg N + 2.
-// Lengths are restricted to {2^a, 3 * 2^a, 5 * 2^a} (smooth lengths,
+// Lengths are restricted to {2^a, 3 * 2^a, 5 * 2^a, 7 * 2^a} (smooth lengths,
 // Section 2.2) and split as M = N/2 = L1 * Lm * L2.
 #pragma once
 #include <math.h>
@@ -56,7 +56,7 @@ inline int lg_ceil(uint64_t x)
 inline bool l1_supported(uint64_t x)
 {
     if (x < 2 || x > L1_MAX) return false;
-    uint64_t y = x % 3 == 0 ? x / 3 : x % 5 == 0 ? x / 5 : x;
+    uint64_t y = x % 3 == 0 ? x / 3 : x % 5 == 0 ? x / 5 : x % 7 == 0 ? x / 7 : x;
     return (y & (y - 1)) == 0;
 }
 
@@ -66,7 +66,7 @@ inline bool split_M(uint64_t M, uint32_t& L1, uint32_t& L2)
     int a = 0;
     while (((M >> a) & 1) == 0) a++;
     uint64_t odd = M >> a;
-    if (odd != 1 && odd != 3 && odd != 5) return false;
+    if (odd != 1 && odd != 3 && odd != 5 && odd != 7) return false;
     int lg = (lg_ceil(M) + 1) / 2;
     if (lg < 4) lg = 4;
     if (lg > 10) lg = 10;
@@ -95,7 +95,7 @@ inline bool split_M3(uint64_t M, uint32_t force_lm, uint32_t& L1, uint32_t& Lm, 
     return false;
 }
 
-// smallest N in {2^a, 3*2^a, 5*2^(a>=5)}, N >= max(x, 64)
+// smallest N in {2^a, 3*2^a, 5*2^(a>=5), 7*2^(a>=5)}, N >= max(x, 64)
 inline uint64_t next_smooth(uint64_t x)
 {
     if (x < 64) x = 64;
@@ -106,6 +106,7 @@ inline uint64_t next_smooth(uint64_t x)
         if (a < 60 && 3 * p2 >= x && 3 * p2 < best) best = 3 * p2;
         // 5 * 2^a from a = 5 on, so that M = N/2 keeps a row length of 16
         if (a >= 5 && a < 59 && 5 * p2 >= x && 5 * p2 < best) best = 5 * p2;
+        if (a >= 5 && a < 59 && 7 * p2 >= x && 7 * p2 < best) best = 7 * p2;
     }
     return best;
 }

@@ -273,6 +273,20 @@ def test_radix5_lengths(n):
     check_all(u, v, n, threads=16)
 
 
+@pytest.mark.parametrize("n", [57344, 75000, 1800000, 20000000])
+def test_radix7_lengths(n):
+    """Lengths 7 * 2^a (radix-7 column stages): n = 57344 gives the full
+    product 2N = 7168 (L1 = 56), n = 75000 the truncated N = 7168, n = 1.8e6
+    the full 2N = 229376 (L1 = 224), n = 2e7 the truncated N = 1835008
+    (L1 = 896, the largest radix-7 column)."""
+    tm = _tm()
+    plans = {k: tm.plan(k, n) for k in ("lo", "hi", "full")}
+    say("[parity] radix-7 n=%d" % n, {k: (p["N"], p["L1"], p["L2"]) for k, p in plans.items()})
+    assert any(p["N"] % 7 == 0 for p in plans.values())
+    u, v = inputs.operand_pair(n, 90)
+    check_all(u, v, n, threads=16)
+
+
 @pytest.mark.parametrize("n,lm", [(65536, 0), (100003, 0), (65536, 4), (1 << 22, 0)])
 def test_squaring_one_transform(monkeypatch, n, lm):
     """u == v (one pointer) takes the squaring path (one forward transform);

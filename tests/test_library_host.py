@@ -59,7 +59,7 @@ def test_plans_satisfy_theorem_constraints(n):
         odd = p["N"]
         while odd % 2 == 0:
             odd //= 2
-        assert odd in (1, 3, 5)
+        assert odd in (1, 3, 5, 7)
 
 
 def test_every_small_size_has_kernels():
@@ -67,7 +67,7 @@ def test_every_small_size_has_kernels():
     with a K2 instance (16..1024) and a column length in the instance list."""
     import paper_1703_00640_amd as tm
     l1_ok = {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024,
-             5, 10, 20, 40, 80, 160, 320, 640}
+             5, 10, 20, 40, 80, 160, 320, 640, 7, 14, 28, 56, 112, 224, 448, 896}
     sizes = list(range(1, 4097)) + list(range(4097, 1 << 17, 97)) + [10 ** 6, 3 * 10 ** 6, 10 ** 7]
     for n in sizes:
         for kind in ("lo", "hi", "full"):
