@@ -244,6 +244,44 @@ def small_latency_bench(log2n=16, reps=200):
     return res
 
 
+def mulmod_bench(log2n=24, reps=10):
+    """Barrett modular multiplication (tm_mulmod: one full, one high and one
+    low product plus carry fixups) at n = 2^24 with the modulus 2^n - 1,
+    whose reciprocal floor(2^(2n) / m) is 2^n + 1; time against one full
+    product of the same size."""
+    import torch
+    import paper_1703_00640_amd as tm
+    from paper_1703_00640_amd import inputs
+    n = 1 << log2n
+    L = n // 64
+    dev = torch.device("cuda:0")
+    a, b = inputs.operand_pair(n, 9)
+    da = torch.from_numpy(a.view(np.int64)).to(dev)
+    db = torch.from_numpy(b.view(np.int64)).to(dev)
+    m = torch.full((L,), -1, dtype=torch.int64, device=dev)
+    mu = torch.zeros(n // 64 + 1, dtype=torch.int64, device=dev)
+    mu[0] = 1
+    mu[L] = 1
+    ws = torch.empty(tm._load().tm_workspace_bytes_mulmod(n), dtype=torch.uint8, device=dev)
+    out = torch.empty(L, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    res = {"n_bits": n, "modulus": "2^n - 1"}
+    for name, fn in (("mulmod_ms", lambda: tm.mulmod(da, db, m, mu, n, out=out, workspace=ws)),
+                     ("full_ms", lambda: tm.mul("full", da, db, n))):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = round(e0.elapsed_time(e1) / reps, 4)
+    res["ratio_to_full"] = round(res["mulmod_ms"] / res["full_ms"], 3)
+    return res
+
+
 def precision_bench(log2n=26, reps=5):
     """The high product at n = 2^26 (the precision-comparison size): the
     maximum rounding distance over all coefficients (the guard) and the time
@@ -461,6 +499,7 @@ def main():
     if not args.no_precision:
         result["precision"] = precision_bench()
         result["small_n"] = small_latency_bench()
+        result["mulmod"] = mulmod_bench()
     if not args.no_serve:
         result["serving"] = serving_bench()
     if not args.no_cpu:

@@ -274,6 +274,26 @@ tm_status tm_profile_stages(tm_kind kind, uint64_t* w, const uint64_t* u, const 
 tm_status tm_prepare(tm_kind kind, uint64_t n_bits, hipStream_t stream);
 
 /*
+ * Barrett modular multiplication, a consumer of the truncated products
+ * (Section 1 names the high product for quotients and the low product for
+ * remainders): r = a b mod m for n_bits-bit a, b (any values below
+ * 2^n_bits), a modulus with 2^(n-1) < m < 2^n (top bit set, not a power of
+ * two), and mu = floor(2^(2n) / m), which has n + 1 bits, supplied by the
+ * caller (computed once per modulus).  Steps on `stream`: x = a b (full
+ * product), q1 = floor(x / 2^(n-1)), w = high product of q1 and mu at n + 1
+ * bits, y = low product of w and m at n + 2 bits, r = x - y mod 2^(n+2),
+ * then one conditional + m and two conditional - m (carry scans on the
+ * device).  Device pointers: r, a, b, m with ceil(n/64) limbs, mu with
+ * ceil((n+1)/64) limbs.  Workspace: tm_workspace_bytes_mulmod(n) bytes,
+ * 256-byte aligned.  n_bits >= 2.  A wrong mu gives a wrong r, never an
+ * out-of-bounds access.
+ */
+size_t tm_workspace_bytes_mulmod(uint64_t n_bits);  /* 0 if unsupported */
+tm_status tm_mulmod(uint64_t* r, const uint64_t* a, const uint64_t* b, const uint64_t* m,
+                    const uint64_t* mu, uint64_t n_bits, void* workspace, size_t workspace_bytes,
+                    hipStream_t stream);
+
+/*
  * Serving: continuous batching on the current device.
  *
  * A server owns one device memory pool of pool_bytes (allocated at

@@ -19,6 +19,11 @@ Contents
 ``coeffs.py``
     Exact rational series coefficients alpha, beta, gamma, delta
     (Sections 3.2 and 4.2) from their binomial definitions.
+``mulmod`` / ``barrett_mu`` (below)
+    Modular multiplication, the consumer of the high and low products that
+    Section 1 names, by its plain definition: the oracle's full product
+    reduced mod m with integer division; and the Barrett reciprocal
+    floor(2^(2n) / m).
 """
 import ctypes
 import os
@@ -145,3 +150,19 @@ def to_int(limbs):
 def from_int(x, L):
     """Python int (non-negative, < 2^(64L)) -> L little-endian uint64 limbs."""
     return np.frombuffer(int(x).to_bytes(8 * L, "little"), dtype="<u8").astype(np.uint64)
+
+
+def mulmod(a, b, m, n_bits, threads=1):
+    """a b mod m (plain definition: the full product, then the remainder of
+    integer division); a, b, m as limb arrays of ceil(n/64) limbs."""
+    L = nlimbs(n_bits)
+    full = to_int(mul_full(a, b, n_bits, threads))
+    return from_int(full % to_int(_limbs(m, L)), L)
+
+
+def barrett_mu(m, n_bits):
+    """floor(2^(2n) / m) as ceil((n+1)/64) limbs (an input of the Barrett
+    reduction, computed once per modulus)."""
+    L = nlimbs(n_bits)
+    mu = (1 << (2 * int(n_bits))) // to_int(_limbs(m, L))
+    return from_int(mu, nlimbs(n_bits + 1))

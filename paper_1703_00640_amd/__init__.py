@@ -17,7 +17,7 @@ import torch
 __all__ = ["mul", "mul_lo", "mul_hi", "mul_full", "mul_batched", "mul_checked",
            "coefficients", "profile_stages", "plan", "workspace_bytes", "Guard",
            "TmulError", "KINDS", "library_path", "prepare", "Server", "serve_trace",
-           "server_footprint", "autotune"]
+           "server_footprint", "autotune", "mulmod"]
 
 KINDS = {"full": 0, "lo": 1, "hi": 2}
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -97,6 +97,10 @@ def _load():
     for name in ("tm_plan_query", "tm_mul", "tm_mul_full", "tm_mul_lo", "tm_mul_hi",
                  "tm_mul_batched", "tm_mul_checked", "tm_coefficients", "tm_profile_stages"):
         getattr(lib, name).restype = I32
+    lib.tm_workspace_bytes_mulmod.argtypes = [U64]
+    lib.tm_workspace_bytes_mulmod.restype = SZ
+    lib.tm_mulmod.argtypes = [P, P, P, P, P, U64, P, SZ, P]
+    lib.tm_mulmod.restype = I32
     lib.tm_prepare.argtypes = [I32, U64, P]
     lib.tm_prepare.restype = I32
     lib.tm_server_footprint.argtypes = [I32, U64]
@@ -346,6 +350,26 @@ def autotune(kind, n_bits, stream=None, device=None):
     _check(_load().tm_autotune(_kind(kind), int(n_bits), _stream_ptr(stream, dev),
                                ctypes.byref(info)), "autotune")
     return {k: getattr(info, k) for k, _ in _PlanInfo._fields_}
+
+
+def mulmod(a, b, m, mu, n_bits, out=None, workspace=None, stream=None):
+    """Barrett modular multiplication r = a b mod m on the GPU (tm_mulmod):
+    a, b, m device tensors of ceil(n/64) limbs with 2^(n-1) < m < 2^n, mu of
+    ceil((n+1)/64) limbs holding floor(2^(2n) / m).  Returns r (n-bit)."""
+    lib = _load()
+    L, L1 = nlimbs(n_bits), nlimbs(n_bits + 1)
+    dev = a.device
+    nb = lib.tm_workspace_bytes_mulmod(int(n_bits))
+    if nb == 0:
+        raise TmulError("mulmod: unsupported size %d" % n_bits)
+    if out is None:
+        out = torch.empty(L, dtype=torch.int64, device=dev)
+    ws = _workspace(nb, dev, workspace)
+    _check(lib.tm_mulmod(_dev_ptr(out, L, "out"), _dev_ptr(a, L, "a"), _dev_ptr(b, L, "b"),
+                         _dev_ptr(m, L, "m"), _dev_ptr(mu, L1, "mu"), int(n_bits),
+                         ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                         _stream_ptr(stream, dev)), "tm_mulmod")
+    return out
 
 
 def server_footprint(kind, n_bits):
