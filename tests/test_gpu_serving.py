@@ -67,7 +67,8 @@ def test_same_alone_and_in_the_mix():
 
 def test_server_submit_poll_and_small_pool():
     """Incremental API with a pool that holds about two of the largest
-    requests: admission waits for memory, results stay exact."""
+    requests: admission waits for memory, results stay exact, with pinned
+    and pageable host buffers mixed in one batch."""
     tm = _tm()
     mix = inputs.serving_mix(24, seed=21, log2_lo=12, log2_hi=16)
     biggest = max(tm.server_footprint(k, n) for k, n in mix)
@@ -76,9 +77,13 @@ def test_server_submit_poll_and_small_pool():
     bufs = {}
     for i, (k, n) in enumerate(mix):
         L = inputs.nlimbs(n)
-        u = torch.from_numpy(pool[offs[i][0]:offs[i][0] + L].view(np.int64).copy()).pin_memory()
-        v = torch.from_numpy(pool[offs[i][1]:offs[i][1] + L].view(np.int64).copy()).pin_memory()
-        out = torch.zeros((2 if k == "full" else 1) * L, dtype=torch.int64).pin_memory()
+        u = torch.from_numpy(pool[offs[i][0]:offs[i][0] + L].view(np.int64).copy())
+        v = torch.from_numpy(pool[offs[i][1]:offs[i][1] + L].view(np.int64).copy())
+        out = torch.zeros((2 if k == "full" else 1) * L, dtype=torch.int64)
+        if i % 3:
+            # pinned buffers are copied by the server's kernels; pageable
+            # ones (every third request) with hipMemcpyAsync
+            u, v, out = u.pin_memory(), v.pin_memory(), out.pin_memory()
         rid = srv.submit(k, u, v, n, out)
         bufs[rid] = (k, n, u, v, out)
     say("submitted", len(bufs), "pending", srv.pending())
