@@ -119,7 +119,8 @@ typedef struct {
 
 /*
  * Autotuner: time every FFT split the planner allows for (kind, n_bits)
- * (the planner's own and each forced middle length Lm) on this device, on
+ * (the planner's own, each forced middle length Lm, and for each Lm the row
+ * lengths L2 twice and half the planner's) on this device, on
  * `stream`, with pseudo-random operands in buffers of its own (it allocates
  * and frees them, and synchronises), and keep the fastest for later calls
  * of this process.  The split changes neither N nor b, so results are the

@@ -10,16 +10,20 @@
 
 namespace tmul {
 
-// column tile width: the largest power of two W <= 8 with L1 W <= tile
-constexpr int w_for(int L1, int tile)
+// column tile width: the largest power of two W <= wmax with L1 W <= tile.
+// K3 and the full product's K1 take up to 16 columns (256-byte row
+// segments: 25-30% faster than 8 for column lengths <= 256); the truncated
+// products' K1 stays at 8 (its digit rows with the map halo need the
+// registers).
+constexpr int w_for(int L1, int tile, int wmax)
 {
-    int lim = tile / L1 < 8 ? tile / L1 : 8;
+    int lim = tile / L1 < wmax ? tile / L1 : wmax;
     int w = 1;
     while (w * 2 <= lim) w *= 2;
     return w;
 }
-constexpr int w1_for(int L1) { return w_for(L1, TILE1); }
-constexpr int w3_for(int L1) { return w_for(L1, TILE3); }
+constexpr int w1_for(int kind, int L1) { return w_for(L1, TILE1, kind == K_FULL ? 16 : 8); }
+constexpr int w3_for(int L1) { return w_for(L1, TILE3, 16); }
 
 #define TM_L1_LIST(X) \
     X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) \
@@ -40,7 +44,7 @@ bool launch_k1_b(uint32_t L1, const KParams& p, hipStream_t s)
 {
     switch (L1) {
 #define X(V) \
-    case V: hipLaunchKernelGGL((k1_split_map_col<V, w1_for(V), KIND, B>), dim3(p.R / w1_for(V), p.zb == p.za ? 1 : 2), dim3(NT1), 0, s, p); return true;
+    case V: hipLaunchKernelGGL((k1_split_map_col<V, w1_for(KIND, V), KIND, B>), dim3(p.R / w1_for(KIND, V), p.zb == p.za ? 1 : 2), dim3(NT1), 0, s, p); return true;
         TM_L1_LIST(X)
 #undef X
     }
@@ -60,7 +64,7 @@ bool launch_k1g_b(uint32_t L1, const Group& g, uint32_t blocks, hipStream_t s)
 {
     switch (L1) {
 #define X(V) \
-    case V: hipLaunchKernelGGL((k1_split_map_col_g<V, w1_for(V), KIND, B>), dim3(blocks), dim3(NT1), 0, s, g); return true;
+    case V: hipLaunchKernelGGL((k1_split_map_col_g<V, w1_for(KIND, V), KIND, B>), dim3(blocks), dim3(NT1), 0, s, g); return true;
         TM_L1_LIST(X)
 #undef X
     }

@@ -60,7 +60,8 @@ inline bool l1_supported(uint64_t x)
     return (y & (y - 1)) == 0;
 }
 
-inline bool split_M(uint64_t M, uint32_t& L1, uint32_t& L2)
+// M = L1 * L2 with L2 = 2^lg near sqrt(M), or 2^force_lg when given
+inline bool split_M(uint64_t M, uint32_t& L1, uint32_t& L2, int force_lg = 0)
 {
     if (M < 32) return false;
     int a = 0;
@@ -70,6 +71,10 @@ inline bool split_M(uint64_t M, uint32_t& L1, uint32_t& L2)
     int lg = (lg_ceil(M) + 1) / 2;
     if (lg < 4) lg = 4;
     if (lg > 10) lg = 10;
+    if (force_lg) {
+        if (force_lg < 4 || force_lg > 10) return false;
+        lg = force_lg;
+    }
     if (lg > a) lg = a;
     L2 = 1u << lg;
     uint64_t l1 = M / L2;
@@ -78,19 +83,26 @@ inline bool split_M(uint64_t M, uint32_t& L1, uint32_t& L2)
     return true;
 }
 
+// Forced FFT split (the autotuner's choice): low 16 bits the middle length
+// Lm (0: the planner's search, >= 1: exactly that Lm), high bits log2 of the
+// row length L2 (0: near sqrt).
+inline uint32_t split_code(uint32_t lm, int lg2) { return lm | ((uint32_t)lg2 << 16); }
+
 // M = L1 * Lm * L2: the smallest power of two Lm (the middle pass of the
 // three-pass split; 1 = two passes) that keeps the column length L1 <= 1024,
-// or the forced Lm.
-inline bool split_M3(uint64_t M, uint32_t force_lm, uint32_t& L1, uint32_t& Lm, uint32_t& L2)
+// or the forced split.
+inline bool split_M3(uint64_t M, uint32_t force, uint32_t& L1, uint32_t& Lm, uint32_t& L2)
 {
-    if (force_lm > 1) {
+    const uint32_t force_lm = force & 0xffffu;
+    const int force_lg = (int)(force >> 16);
+    if (force_lm >= 1 && (force_lm > 1 || force_lg)) {
         Lm = force_lm;
-        return (Lm & (Lm - 1)) == 0 && Lm <= LM_MAX && M % Lm == 0 && split_M(M / Lm, L1, L2) &&
+        return (Lm & (Lm - 1)) == 0 && Lm <= LM_MAX && M % Lm == 0 && split_M(M / Lm, L1, L2, force_lg) &&
                L1 <= 1024;
     }
     for (Lm = 1; Lm <= LM_MAX; Lm *= 2) {
         if (M % Lm != 0) return false;
-        if (split_M(M / Lm, L1, L2) && L1 <= 1024) return true;
+        if (split_M(M / Lm, L1, L2, force_lg) && L1 <= 1024) return true;
     }
     return false;
 }
@@ -115,7 +127,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Build the plan.  b_trunc / b_full: digit sizes (0 = default).
 // Returns false if unsupported.
-inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P, uint32_t force_lm = 0)
+inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P, uint32_t force = 0)
 {
     if (n == 0 || kind < 0 || kind > 2) return false;
     P = Plan();
@@ -166,7 +178,7 @@ inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P, ui
         P.out_limbs = P.L;
     }
     P.M = P.N / 2;
-    if (!split_M3(P.M, force_lm, P.L1, P.Lm, P.L2)) return false;
+    if (!split_M3(P.M, force, P.L1, P.Lm, P.L2)) return false;
     uint64_t need = (P.off + P.out_bits + P.b - 1) / P.b + 2;
     uint64_t cov = P.ncoef > need ? P.ncoef : need;
     P.ncover = (cov + DPW_HOST - 1) / DPW_HOST * DPW_HOST;

@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -88,16 +89,16 @@ struct TwEntry {
 };
 
 std::mutex g_tw_mu;
-std::map<std::pair<int, uint64_t>, TwEntry> g_tw;
+std::map<std::tuple<int, uint64_t, uint32_t, uint32_t>, TwEntry> g_tw;
 
-// Twiddle tables for transform length M = L1 * L2 (the plan fixes L1, L2
-// from M), built once per device.
+// Twiddle tables for transform length M = L1 * Lm * L2, built once per
+// device and split (the sub-transform tables depend on L1, Lm and L2).
 tm_status get_twiddles(uint64_t M, uint32_t L1, uint32_t Lm, uint32_t L2, hipStream_t s, TwEntry& out)
 {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_tw_mu);
-    auto key = std::make_pair(dev, M * 512 + Lm);
+    const auto key = std::make_tuple(dev, M, Lm, L2);
     auto it = g_tw.find(key);
     if (it != g_tw.end()) {
         out = it->second;
@@ -280,7 +281,7 @@ bool stage_shape(int st, int kind, const KParams& p, uint64_t& key, uint32_t& nx
     switch (st) {
     case ST_K1:
         key = ((uint64_t)kind << 40) | ((uint64_t)fb << 32) | p.L1;
-        nx = p.R / (uint32_t)w1_for((int)p.L1);
+        nx = p.R / (uint32_t)w1_for(kind == TM_FULL ? K_FULL : kind == TM_LO ? K_LO : K_HI, (int)p.L1);
         ny = p.zb == p.za ? 1 : 2;
         return true;
     case ST_MIDF:
@@ -456,13 +457,14 @@ void fill_params(const Plan& P, const uint64_t* u, const uint64_t* v, uint64_t* 
     p.twm = tw.subm;
 }
 
-// Splits chosen by tm_autotune: (kind, n) -> middle length Lm (0: the
-// planner's own choice).  The split changes only the FFT schedule, not N or
-// b, so tuned and untuned calls return the same products.
+// Splits chosen by tm_autotune: (kind, n) -> split code (middle length Lm
+// and row length L2, see split_code; 0: the planner's own choice).  The
+// split changes only the FFT schedule, not N or b, so tuned and untuned
+// calls return the same products.
 std::mutex g_tune_mu;
 std::map<std::pair<int, uint64_t>, uint32_t> g_tuned;
 
-uint32_t tuned_lm(tm_kind kind, uint64_t n)
+uint32_t tuned_split(tm_kind kind, uint64_t n)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(std::make_pair((int)kind, n));
@@ -489,10 +491,13 @@ tm_status plan_for(tm_kind kind, uint64_t n, Plan& P, int bt = 0, int bf = 0)
     }
     uint32_t flm = 0;
     {
+        // forced split (tests, experiments): middle length, log2 row length
         const char* e = getenv("TM_FORCE_LM");
         if (e && *e) flm = (uint32_t)atoi(e);
+        const char* e2 = getenv("TM_FORCE_LG2");
+        if (e2 && *e2) flm = split_code(flm, atoi(e2));
     }
-    if (!flm) flm = tuned_lm(kind, n);
+    if (!flm) flm = tuned_split(kind, n);
     if (!make_plan((int)kind, n, bt, bf, P, flm)) {
         g_last_error = "unsupported size";
         return TM_ERR_UNSUPPORTED;
@@ -762,11 +767,25 @@ tm_status tm_autotune(tm_kind kind, uint64_t n_bits, hipStream_t stream, tm_plan
     Plan P0;
     tm_status st = plan_for(kind, n_bits, P0);
     if (st != TM_OK) return st;
-    // candidates: the planner's split and every forced middle length
+    // candidates: the planner's split, every forced middle length, and for
+    // each middle length the row lengths twice and half the planner's
     std::vector<uint32_t> cand{0};
-    for (uint32_t lm = 2; lm <= LM_MAX; lm *= 2) {
+    std::vector<std::pair<uint32_t, uint32_t>> seen{{P0.Lm, P0.L2}};
+    for (uint32_t lm = 1; lm <= LM_MAX; lm *= 2) {
         Plan Q;
-        if (make_plan((int)kind, n_bits, 0, 0, Q, lm) && Q.Lm != P0.Lm) cand.push_back(lm);
+        if (!make_plan((int)kind, n_bits, 0, 0, Q, split_code(lm, 0)) || Q.Lm != lm) continue;
+        const int lg = lg_ceil(Q.L2);
+        for (int lg2 : {0, lg + 1, lg - 1}) {
+            Plan S;
+            const uint32_t code = split_code(lm, lg2);
+            if (!make_plan((int)kind, n_bits, 0, 0, S, code)) continue;
+            const std::pair<uint32_t, uint32_t> key{S.Lm, S.L2};
+            bool dup = false;
+            for (auto& k : seen) dup = dup || k == key;
+            if (dup) continue;
+            seen.push_back(key);
+            cand.push_back(code);
+        }
     }
     uint32_t best = 0;
     if (cand.size() > 1) {

@@ -329,6 +329,37 @@ def test_autotune_keeps_products():
         assert np.array_equal(run_kind(k, u, v, n, guard=False)[0], before[k])
 
 
+@pytest.mark.parametrize("n", [1 << 20, 3000000])
+def test_every_row_length_keeps_products(monkeypatch, n):
+    """Every row length L2 the planner accepts (forced as the autotuner
+    forces it) gives the default split's products bit for bit, including
+    the wide-column K1/K3 instances of short columns."""
+    tm = _tm()
+    u, v = inputs.operand_pair(n, 91)
+    want = {"lo": oracle.mul_lo(u, v, n, 16), "full": oracle.mul_full(u, v, n, 16)}
+    q, nz = oracle.mul_hi(u, v, n, 16)
+    bad = []
+    for k in ("lo", "hi", "full"):
+        base = run_kind(k, u, v, n, guard=False)[0]
+        seen = set()
+        for lg2 in range(4, 11):
+            monkeypatch.setenv("TM_FORCE_LG2", str(lg2))
+            try:
+                p = tm.plan(k, n)
+            except tm.TmulError:
+                continue
+            split = (p["L1"], p["Lm"], p["L2"])
+            seen.add(split)
+            w, g = run_kind(k, u, v, n)
+            ok = np.array_equal(w, want[k]) if k != "hi" else oracle.hi_accepts(w, q, nz)
+            if not ok or not np.array_equal(w, base) or g.flags:
+                bad.append((k, split, ok, g.flags))
+        monkeypatch.delenv("TM_FORCE_LG2")
+        say("[parity] %s n=%d splits" % (k, n), sorted(seen))
+        assert len(seen) >= 2
+    assert not bad, bad
+
+
 def test_config_n2_26_parity():
     """n = 2^26 (three-pass split chosen automatically): lo, hi, full vs the
     oracle."""
