@@ -123,7 +123,8 @@ typedef struct {
  * lengths L2 twice and half the planner's) on this device, on
  * `stream`, with pseudo-random operands in buffers of its own (it allocates
  * and frees them, and synchronises), and keep the fastest for later calls
- * of this process.  The split changes neither N nor b, so results are the
+ * of this process (fastest of five timed runs per split).  The split changes
+ * neither N nor b, so results are the
  * same as untuned.  *chosen (may be NULL) receives the tuned plan.
  */
 tm_status tm_autotune(tm_kind kind, uint64_t n_bits, hipStream_t stream, tm_plan_info* chosen);

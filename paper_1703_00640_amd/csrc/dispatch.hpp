@@ -11,10 +11,12 @@
 namespace tmul {
 
 // column tile width: the largest power of two W <= wmax with L1 W <= tile.
-// K3 and the full product's K1 take up to 16 columns (256-byte row
-// segments: 25-30% faster than 8 for column lengths <= 256); the truncated
-// products' K1 stays at 8 (its digit rows with the map halo need the
-// registers).
+// With the three-pass split (large transforms, many column tiles) K3 and
+// the full product's K1 take up to 16 columns: 256-byte row segments are
+// 25-30% faster than 128-byte ones at n = 2^30 for columns up to 256.
+// Two-pass splits (smaller sizes) keep 8, which gives twice the workgroups
+// and lower latency; so does the truncated products' K1 always (its digit
+// rows with the map halo need the registers).
 constexpr int w_for(int L1, int tile, int wmax)
 {
     int lim = tile / L1 < wmax ? tile / L1 : wmax;
@@ -22,8 +24,9 @@ constexpr int w_for(int L1, int tile, int wmax)
     while (w * 2 <= lim) w *= 2;
     return w;
 }
-constexpr int w1_for(int kind, int L1) { return w_for(L1, TILE1, kind == K_FULL ? 16 : 8); }
-constexpr int w3_for(int L1) { return w_for(L1, TILE3, 16); }
+constexpr int w1_for(int kind, int L1, bool wide) { return w_for(L1, TILE1, kind == K_FULL && wide ? 16 : 8); }
+constexpr int w3_for(int L1, bool wide) { return w_for(L1, TILE3, wide ? 16 : 8); }
+inline bool wide_tiles(const KParams& p) { return p.Lm > 1; }
 
 #define TM_L1_LIST(X) \
     X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) \
@@ -44,7 +47,14 @@ bool launch_k1_b(uint32_t L1, const KParams& p, hipStream_t s)
 {
     switch (L1) {
 #define X(V) \
-    case V: hipLaunchKernelGGL((k1_split_map_col<V, w1_for(KIND, V), KIND, B>), dim3(p.R / w1_for(KIND, V), p.zb == p.za ? 1 : 2), dim3(NT1), 0, s, p); return true;
+    case V:                                                                                              \
+        if (wide_tiles(p))                                                                               \
+            hipLaunchKernelGGL((k1_split_map_col<V, w1_for(KIND, V, true), KIND, B>),                    \
+                               dim3(p.R / w1_for(KIND, V, true), p.zb == p.za ? 1 : 2), dim3(NT1), 0, s, p); \
+        else                                                                                             \
+            hipLaunchKernelGGL((k1_split_map_col<V, w1_for(KIND, V, false), KIND, B>),                   \
+                               dim3(p.R / w1_for(KIND, V, false), p.zb == p.za ? 1 : 2), dim3(NT1), 0, s, p); \
+        return true;
         TM_L1_LIST(X)
 #undef X
     }
@@ -60,11 +70,16 @@ bool launch_k1(uint32_t L1, const KParams& p, hipStream_t s)
 // Packed launch of one K1 instance over the requests of group g (`blocks`
 // workgroups in total); fb: the requests' common fixed_b().
 template <int KIND, int B>
-bool launch_k1g_b(uint32_t L1, const Group& g, uint32_t blocks, hipStream_t s)
+bool launch_k1g_b(uint32_t L1, bool wide, const Group& g, uint32_t blocks, hipStream_t s)
 {
     switch (L1) {
-#define X(V) \
-    case V: hipLaunchKernelGGL((k1_split_map_col_g<V, w1_for(KIND, V), KIND, B>), dim3(blocks), dim3(NT1), 0, s, g); return true;
+#define X(V)                                                                                                  \
+    case V:                                                                                                   \
+        if (wide)                                                                                             \
+            hipLaunchKernelGGL((k1_split_map_col_g<V, w1_for(KIND, V, true), KIND, B>), dim3(blocks), dim3(NT1), 0, s, g); \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k1_split_map_col_g<V, w1_for(KIND, V, false), KIND, B>), dim3(blocks), dim3(NT1), 0, s, g); \
+        return true;
         TM_L1_LIST(X)
 #undef X
     }
@@ -72,17 +87,17 @@ bool launch_k1g_b(uint32_t L1, const Group& g, uint32_t blocks, hipStream_t s)
 }
 
 template <int KIND, int BF>
-bool launch_k1g(uint32_t L1, int fb, const Group& g, uint32_t blocks, hipStream_t s)
+bool launch_k1g(uint32_t L1, int fb, bool wide, const Group& g, uint32_t blocks, hipStream_t s)
 {
-    return fb ? launch_k1g_b<KIND, BF>(L1, g, blocks, s) : launch_k1g_b<KIND, 0>(L1, g, blocks, s);
+    return fb ? launch_k1g_b<KIND, BF>(L1, wide, g, blocks, s) : launch_k1g_b<KIND, 0>(L1, wide, g, blocks, s);
 }
 
 // defined in k1_full.hip, k1_lo.hip, k1_hi.hip
 bool launch_k1_full(uint32_t L1, const KParams& p, hipStream_t s);
 bool launch_k1_lo(uint32_t L1, const KParams& p, hipStream_t s);
 bool launch_k1_hi(uint32_t L1, const KParams& p, hipStream_t s);
-bool launch_k1g_full(uint32_t L1, int fb, const Group& g, uint32_t blocks, hipStream_t s);
-bool launch_k1g_lo(uint32_t L1, int fb, const Group& g, uint32_t blocks, hipStream_t s);
-bool launch_k1g_hi(uint32_t L1, int fb, const Group& g, uint32_t blocks, hipStream_t s);
+bool launch_k1g_full(uint32_t L1, int fb, bool wide, const Group& g, uint32_t blocks, hipStream_t s);
+bool launch_k1g_lo(uint32_t L1, int fb, bool wide, const Group& g, uint32_t blocks, hipStream_t s);
+bool launch_k1g_hi(uint32_t L1, int fb, bool wide, const Group& g, uint32_t blocks, hipStream_t s);
 
 }  // namespace tmul

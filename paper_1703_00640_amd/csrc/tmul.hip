@@ -143,7 +143,12 @@ bool launch_k3(uint32_t L1, const KParams& p, hipStream_t s)
 {
     switch (L1) {
 #define X(V) \
-    case V: hipLaunchKernelGGL((k3_col_inverse<V, w3_for(V)>), dim3(p.R / w3_for(V)), dim3(NT3), 0, s, p); return true;
+    case V:                                                                                              \
+        if (wide_tiles(p))                                                                               \
+            hipLaunchKernelGGL((k3_col_inverse<V, w3_for(V, true)>), dim3(p.R / w3_for(V, true)), dim3(NT3), 0, s, p); \
+        else                                                                                             \
+            hipLaunchKernelGGL((k3_col_inverse<V, w3_for(V, false)>), dim3(p.R / w3_for(V, false)), dim3(NT3), 0, s, p); \
+        return true;
         TM_L1_LIST(X)
 #undef X
     }
@@ -235,11 +240,16 @@ bool launch_midg(uint32_t Lm, int W, const Group& g, uint32_t blocks, hipStream_
     return false;
 }
 
-bool launch_k3g(uint32_t L1, const Group& g, uint32_t blocks, hipStream_t s)
+bool launch_k3g(uint32_t L1, bool wide, const Group& g, uint32_t blocks, hipStream_t s)
 {
     switch (L1) {
-#define X(V) \
-    case V: hipLaunchKernelGGL((k3_col_inverse_g<V, w3_for(V)>), dim3(blocks), dim3(NT3), 0, s, g); return true;
+#define X(V)                                                                                          \
+    case V:                                                                                           \
+        if (wide)                                                                                     \
+            hipLaunchKernelGGL((k3_col_inverse_g<V, w3_for(V, true)>), dim3(blocks), dim3(NT3), 0, s, g); \
+        else                                                                                          \
+            hipLaunchKernelGGL((k3_col_inverse_g<V, w3_for(V, false)>), dim3(blocks), dim3(NT3), 0, s, g); \
+        return true;
         TM_L1_LIST(X)
 #undef X
     }
@@ -260,11 +270,11 @@ void launch_k4g(int kind, int fb, const Group& g, uint32_t blocks, hipStream_t s
     }
 }
 
-bool launch_k1g_any(int kind, uint32_t L1, int fb, const Group& g, uint32_t blocks, hipStream_t s)
+bool launch_k1g_any(int kind, uint32_t L1, int fb, bool wide, const Group& g, uint32_t blocks, hipStream_t s)
 {
-    if (kind == TM_FULL) return launch_k1g_full(L1, fb, g, blocks, s);
-    if (kind == TM_LO) return launch_k1g_lo(L1, fb, g, blocks, s);
-    return launch_k1g_hi(L1, fb, g, blocks, s);
+    if (kind == TM_FULL) return launch_k1g_full(L1, fb, wide, g, blocks, s);
+    if (kind == TM_LO) return launch_k1g_lo(L1, fb, wide, g, blocks, s);
+    return launch_k1g_hi(L1, fb, wide, g, blocks, s);
 }
 
 // Stages of one multiplication in launch order; the middle passes exist
@@ -277,11 +287,12 @@ bool stage_shape(int st, int kind, const KParams& p, uint64_t& key, uint32_t& nx
                  uint32_t& nz)
 {
     const int fb = fixed_b(kind, p) ? 1 : 0;
+    const bool wide = wide_tiles(p);
     nx = ny = nz = 1;
     switch (st) {
     case ST_K1:
-        key = ((uint64_t)kind << 40) | ((uint64_t)fb << 32) | p.L1;
-        nx = p.R / (uint32_t)w1_for(kind == TM_FULL ? K_FULL : kind == TM_LO ? K_LO : K_HI, (int)p.L1);
+        key = ((uint64_t)wide << 42) | ((uint64_t)kind << 40) | ((uint64_t)fb << 32) | p.L1;
+        nx = p.R / (uint32_t)w1_for(kind, (int)p.L1, wide);
         ny = p.zb == p.za ? 1 : 2;
         return true;
     case ST_MIDF:
@@ -299,8 +310,8 @@ bool stage_shape(int st, int kind, const KParams& p, uint64_t& key, uint32_t& nx
         nx = k2_groups(p.L1, p.Lm);
         return true;
     case ST_K3:
-        key = p.L1;
-        nx = p.R / (uint32_t)w3_for((int)p.L1);
+        key = ((uint64_t)wide << 32) | p.L1;
+        nx = p.R / (uint32_t)w3_for((int)p.L1, wide);
         return true;
     default:
         key = ((uint64_t)kind << 1) | (uint64_t)fb;
@@ -371,6 +382,7 @@ tm_status stage_acquire(int dev, size_t bytes, StageBuf*& out)
 struct Launch {
     int st;
     int kind, fb;
+    bool wide;          // K1/K3: wide column tiles (three-pass split)
     uint32_t a, b;      // instance: K1/K3 L1, K2 L2, middle Lm and W
     uint32_t ent0, nr;  // first table entry, requests
     uint32_t blocks;
@@ -632,6 +644,7 @@ tm_status run_packed(const tm_request* reqs, size_t count, void* const* ws, cons
             const KParams& p0 = ps[order[k].second];
             L.kind = kinds[order[k].second];
             L.fb = fixed_b(L.kind, p0) ? 1 : 0;
+            L.wide = wide_tiles(p0);
             L.a = st == ST_K2 ? p0.L2 : (st == ST_MIDF || st == ST_MIDI) ? p0.Lm : p0.L1;
             L.b = (st == ST_MIDF || st == ST_MIDI) ? (uint32_t)mid_w(p0) : 0;
             uint64_t blocks = 0;
@@ -674,11 +687,11 @@ tm_status run_packed(const tm_request* reqs, size_t count, void* const* ws, cons
         const Group g{dps, dent + L.ent0, L.nr};
         bool ok = true;
         switch (L.st) {
-        case ST_K1: ok = launch_k1g_any(L.kind, L.a, L.fb, g, L.blocks, s); break;
+        case ST_K1: ok = launch_k1g_any(L.kind, L.a, L.fb, L.wide, g, L.blocks, s); break;
         case ST_MIDF: ok = launch_midg<false>(L.a, (int)L.b, g, L.blocks, s); break;
         case ST_K2: ok = launch_k2g(L.a, g, L.blocks, s); break;
         case ST_MIDI: ok = launch_midg<true>(L.a, (int)L.b, g, L.blocks, s); break;
-        case ST_K3: ok = launch_k3g(L.a, g, L.blocks, s); break;
+        case ST_K3: ok = launch_k3g(L.a, L.wide, g, L.blocks, s); break;
         default: launch_k4g(L.kind, L.fb, g, L.blocks, s); break;
         }
         if (!ok) {
@@ -824,17 +837,20 @@ tm_status tm_autotune(tm_kind kind, uint64_t n_bits, hipStream_t stream, tm_plan
         for (uint32_t lm : cand) {
             Plan Q;
             if (!make_plan((int)kind, n_bits, 0, 0, Q, lm)) continue;
+            // one untimed run, then the fastest of five timed ones
             float tot = 0.0f;
-            for (int rep = 0; rep < 4 && st == TM_OK; rep++) {
-                if (rep == 1) st = hipEventRecord(e0, stream) == hipSuccess ? TM_OK : TM_ERR_HIP;
+            for (int rep = 0; rep < 6 && st == TM_OK; rep++) {
+                if (rep > 0) st = hipEventRecord(e0, stream) == hipSuccess ? TM_OK : TM_ERR_HIP;
                 if (st == TM_OK)
                     st = run(Q, static_cast<uint64_t*>(dw), u, u + L, dws, wsb, stream, nullptr, RUN,
                              nullptr, nullptr, nullptr);
+                float t = 0.0f;
+                if (st == TM_OK && rep > 0 &&
+                    (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                     hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+                    st = TM_ERR_HIP;
+                if (st == TM_OK && rep > 0 && (tot == 0.0f || t < tot)) tot = t;
             }
-            if (st == TM_OK && (hipEventRecord(e1, stream) != hipSuccess ||
-                                hipEventSynchronize(e1) != hipSuccess ||
-                                hipEventElapsedTime(&tot, e0, e1) != hipSuccess))
-                st = TM_ERR_HIP;
             if (st != TM_OK) break;
             if (best_ms == 0.0f || tot < best_ms) {
                 best_ms = tot;
