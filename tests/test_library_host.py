@@ -141,6 +141,23 @@ def test_packed_batch_sizes_and_checks():
     assert lib.tm_mul_batched(ctypes.byref(reqs), len(mix), None, 1 << 30, None, None) == 1
 
 
+def test_mulmod_host_checks():
+    """Barrett modular multiplication: workspace sizes (0 below two bits,
+    growing with n) and argument checks before any device work."""
+    import paper_1703_00640_amd as tm
+    lib = tm._load()
+    assert lib.tm_workspace_bytes_mulmod(0) == 0 and lib.tm_workspace_bytes_mulmod(1) == 0
+    small, big = lib.tm_workspace_bytes_mulmod(2), lib.tm_workspace_bytes_mulmod(1 << 20)
+    assert 0 < small < big and big % 256 == 0
+    # the workspace holds the largest of the three products' workspaces
+    assert big >= max(tm.workspace_bytes("full", 1 << 20), tm.workspace_bytes("hi", (1 << 20) + 1),
+                      tm.workspace_bytes("lo", (1 << 20) + 2))
+    assert lib.tm_mulmod(None, None, None, None, None, 521, None, 0, None) == 1
+    assert lib.tm_mulmod(8, 8, 8, 8, 8, 1, 256, 1 << 20, None) == 1          # n < 2
+    assert lib.tm_mulmod(8, 8, 8, 8, 8, 521, 256, 16, None) == 1             # workspace too small
+    assert lib.tm_mulmod(8, 8, 8, 8, 8, 521, 260, 1 << 20, None) == 1        # misaligned workspace
+
+
 def test_three_pass_split_for_large_n():
     """n = 2^30: M = L1 * Lm * L2 with a middle pass; n = 2^24 stays two-pass."""
     lo, full = _plan("lo", 1 << 30), _plan("full", 1 << 30)
