@@ -108,6 +108,29 @@ def pmc_pass(n_bits):
     print("pmc pass done", flush=True)
 
 
+def copy_ceiling_gb_s(mib=256, reps=10):
+    """Achieved bandwidth of a plain device-to-device copy of `mib` MiB
+    (read + write bytes per second): the practical ceiling the kernels'
+    algorithmic GB/s is also compared against."""
+    import torch
+    dev = torch.device("cuda:0")
+    a = torch.ones(mib << 17, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * a.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
+
+
 def large_n_bench(log2n, steps):
     """The three products at one large size (n = 2^30 by default: the
     largest single instance), per kind and per kernel, with each kernel's
@@ -150,6 +173,9 @@ def large_n_bench(log2n, steps):
         res["hbm_frac"][k] = {nm: round(nb[nm] / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 3) for nm, t in st.items()}
         del ws, out
         torch.cuda.empty_cache()
+    ceil = copy_ceiling_gb_s()
+    res["copy_ceiling_gb_s"] = ceil
+    res["copy_frac"] = {k: {nm: round(g / ceil, 3) for nm, g in v.items()} for k, v in res["stage_gb_s"].items()}
     res["ratio_lo_full"] = round(res["ms"]["lo"] / res["ms"]["full"], 4)
     res["ratio_hi_full"] = round(res["ms"]["hi"] / res["ms"]["full"], 4)
     res["mbit_s"] = {k: round(n / (res["ms"][k] * 1e-3) / 1e6, 1) for k in res["ms"]}
