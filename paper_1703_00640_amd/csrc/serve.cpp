@@ -16,6 +16,7 @@
 // requests).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstdio>
 #include <cstring>
@@ -81,9 +82,13 @@ private:
     std::map<size_t, size_t> free_;
 };
 
+// A request's own pool block holds its workspace and operands; its result
+// goes to its batch's result region, where the results of a batch are
+// contiguous (so results bound for contiguous host memory leave in one copy).
 struct Layout {
-    size_t u, v, w, ws, total;  // offsets inside the request's block
-    size_t ub, wb, wsb;         // bytes of u (= v), w and workspace
+    size_t u, v, ws, total;  // offsets inside the request's block, block bytes
+    size_t ub, wb, wsb;      // bytes of u (= v), w and workspace
+    size_t footprint;        // block + result bytes (tm_server_footprint)
 };
 
 bool layout_for(tm_kind kind, uint64_t n, Layout& l)
@@ -98,8 +103,8 @@ bool layout_for(tm_kind kind, uint64_t n, Layout& l)
     l.ws = o; o = align_up(o + ws);
     l.u = o; o = align_up(o + l.ub);
     l.v = o; o = align_up(o + l.ub);
-    l.w = o; o = align_up(o + l.wb);
     l.total = o;
+    l.footprint = o + align_up(l.wb);
     return true;
 }
 
@@ -118,6 +123,7 @@ struct Batch {
     std::vector<Job> jobs;
     int stream = -1;
     size_t meta_off = 0;
+    size_t res_off = 0, res_bytes = 0;  // result region: the jobs' results in order
     hipEvent_t done = nullptr;
     tm_guard* guards_host = nullptr;  // pinned staging of the batch's guards
 };
@@ -159,6 +165,7 @@ tm_status launch(tm_server* s, Batch& b)
     std::vector<void*> wss(k);
     std::vector<size_t> wsb(k);
     std::vector<tm_guard*> gs(k);
+    size_t wpos = 0;
     for (size_t i = 0; i < k; i++) {
         Job& j = b.jobs[i];
         char* blk = s->base + j.off;
@@ -173,7 +180,8 @@ tm_status launch(tm_server* s, Batch& b)
         reqs[i] = j.req;
         reqs[i].u = du;
         reqs[i].v = dv;
-        reqs[i].w = reinterpret_cast<uint64_t*>(blk + j.lay.w);
+        reqs[i].w = reinterpret_cast<uint64_t*>(s->base + b.res_off) + wpos;
+        wpos += j.lay.wb / 8;
         wss[i] = blk + j.lay.ws;
         wsb[i] = j.lay.wsb;
         gs[i] = dg + i;
@@ -183,10 +191,18 @@ tm_status launch(tm_server* s, Batch& b)
                          : tm_mul_packed(reqs.data(), k, wss.data(), wsb.data(), meta, batch_guard_offset(), st,
                                          gs.data());
     if (r != TM_OK) return r;
-    for (size_t i = 0; i < k; i++) {
-        Job& j = b.jobs[i];
-        if (hipMemcpyAsync(j.req.w, reqs[i].w, j.lay.wb, hipMemcpyDeviceToHost, st) != hipSuccess)
+    // results: one copy per run of requests whose host buffers follow each
+    // other (the device results of a batch are contiguous)
+    for (size_t i = 0; i < k;) {
+        size_t bytes = b.jobs[i].lay.wb, e = i + 1;
+        while (e < k && reinterpret_cast<char*>(b.jobs[e - 1].req.w) + b.jobs[e - 1].lay.wb ==
+                            reinterpret_cast<char*>(b.jobs[e].req.w)) {
+            bytes += b.jobs[e].lay.wb;
+            e++;
+        }
+        if (hipMemcpyAsync(b.jobs[i].req.w, reqs[i].w, bytes, hipMemcpyDeviceToHost, st) != hipSuccess)
             return TM_ERR_HIP;
+        i = e;
     }
     if (s->spare_guards.empty()) {
         void* h = nullptr;
@@ -211,6 +227,7 @@ tm_status launch(tm_server* s, Batch& b)
 void release_batch(tm_server* s, Batch& b)
 {
     for (auto& j : b.jobs) s->pool.release(j.off, j.lay.total);
+    if (b.res_bytes) s->pool.release(b.res_off, b.res_bytes);
     s->pool.release(b.meta_off, batch_block_bytes());
     if (b.done) s->spare_events.push_back(b.done);
     if (b.guards_host) s->spare_guards.push_back(b.guards_host);
@@ -269,21 +286,41 @@ void admit(tm_server* s)
                s->n_running + cur.jobs.size() < s->max_inflight) {
             Job& j = *it;
             size_t off;
-            const bool room = s->pool.free_bytes() >= reserved + j.lay.total;
+            const bool room = s->pool.free_bytes() >= reserved + j.lay.footprint;
             if (room && s->pool.alloc(j.lay.total, off)) {
                 j.off = off;
                 cur.jobs.push_back(j);
                 it = s->waiting.erase(it);
             } else {
-                reserved += j.lay.total;
+                reserved += j.lay.footprint;
                 ++it;
             }
+        }
+        // the batch's result region: if it does not fit, requests go back
+        // to the queue (in submission order) from the end of the batch
+        bool shrunk = false;
+        while (!cur.jobs.empty()) {
+            size_t rb = 0;
+            for (const Job& j : cur.jobs) rb += j.lay.wb;
+            rb = align_up(rb);
+            if (s->pool.alloc(rb, cur.res_off)) {
+                cur.res_bytes = rb;
+                break;
+            }
+            const Job j = cur.jobs.back();
+            cur.jobs.pop_back();
+            s->pool.release(j.off, j.lay.total);
+            auto pos = std::upper_bound(s->waiting.begin(), s->waiting.end(), j.id,
+                                        [](uint64_t id, const Job& w) { return id < w.id; });
+            s->waiting.insert(pos, j);
+            shrunk = true;
         }
         if (cur.jobs.empty()) {
             s->pool.release(cur.meta_off, batch_block_bytes());
             break;
         }
         start(s, cur);
+        if (shrunk) break;  // the queue changed under the iterator
     }
 }
 
@@ -316,7 +353,7 @@ extern "C" {
 size_t tm_server_footprint(tm_kind kind, uint64_t n_bits)
 {
     Layout l;
-    return layout_for(kind, n_bits, l) ? l.total : 0;
+    return layout_for(kind, n_bits, l) ? l.footprint : 0;
 }
 
 tm_status tm_server_create(size_t pool_bytes, int n_streams, int max_inflight, tm_server** out)
@@ -350,7 +387,7 @@ tm_status tm_server_submit(tm_server* s, const tm_request* req, tm_guard* guard_
     if (!s || !req || !req->u || !req->v || !req->w || req->kind > 2) return TM_ERR_INVALID;
     Job j;
     if (!layout_for((tm_kind)req->kind, req->n_bits, j.lay)) return TM_ERR_UNSUPPORTED;
-    if (j.lay.total + batch_block_bytes() > s->pool.size()) return TM_ERR_INVALID;  // can never be admitted
+    if (j.lay.footprint + batch_block_bytes() > s->pool.size()) return TM_ERR_INVALID;  // can never be admitted
     j.id = s->next_id++;
     j.req = *req;
     j.guard_host = guard_host;
