@@ -1,21 +1,26 @@
 """Benchmark: truncated vs full product on one MI355X.
 
 A step is one low product, one high product and one full product of the same
-two n-bit operands (n = 2^24 by default: uniform random 64-bit limbs from a
-fixed seed), inputs resident in HBM.  Prints one JSON line with
+two n-bit operands (n = 2^30 by default, the largest single instance:
+uniform random 64-bit limbs from a fixed seed), inputs resident in HBM.
+Prints one JSON line with
 
 * value: whole-step operand throughput, 3 n bits / step time, in Mbit/s;
 * per-kind time and Mbit/s, and the lo/full and hi/full time ratios;
-* roofline: algorithmic bytes / time of the dominant kernel, timed with HIP
-  events on the launch stream, against the 8 TB/s HBM peak;
-* large_n: the same three products at n = 2^30 (the largest single
-  instance), per kind and per kernel, with each kernel's fraction of the HBM
-  peak;
-* serving: p50 / p99 latency and throughput of a mixed stream of requests
-  (n from 2^12 to 2^22 bits, all three kinds) through the library's
-  continuous-batching server, saturated and under Poisson arrivals;
-* cpu_baseline: the CPU oracle (Karatsuba on 64-bit limbs) computing the
-  same three products for one operand pair, timed on the host cores.
+* per-kernel times (HIP events on the launch stream), each kernel's
+  algorithmic GB/s against the 8 TB/s HBM peak and a measured copy ceiling;
+* roofline: algorithmic bytes / time of the dominant (longest) kernel;
+* n2_24: the same step at n = 2^24 (operands and transforms fit the 256 MiB
+  last-level cache, so its GB/s are effective figures);
+* precision: rounding distances at n = 2^26 for several digit sizes, and
+  the edge-digit pattern through the checked entry point;
+* serving: throughput (saturated) and p50 / p99 latency (Poisson arrivals)
+  of a mixed stream of requests (n from 2^12 to 2^22 bits, all three kinds)
+  through the library's continuous-batching server;
+* cpu_baseline: the CPU oracle (Karatsuba on 64-bit limbs) on the host cores.
+
+Every guard of the timed products is read; a tripped guard aborts the run.
+Progress goes to stderr.
 """
 import argparse
 import json
@@ -92,7 +97,7 @@ def pmc_pass(n_bits):
     import paper_1703_00640_amd as tm
     from paper_1703_00640_amd import inputs
     dev = torch.device("cuda:0")
-    u, v = inputs.operand_pair(n_bits, 2)
+    u, v = inputs.operand_pair(n_bits, 5)
     du = torch.from_numpy(u.view(np.int64)).to(dev)
     dv = torch.from_numpy(v.view(np.int64)).to(dev)
     for k in ("lo", "hi", "full"):
@@ -131,57 +136,6 @@ def copy_ceiling_gb_s(mib=256, reps=10):
     return round(gbs, 1)
 
 
-def large_n_bench(log2n, steps):
-    """The three products at one large size (n = 2^30 by default: the
-    largest single instance), per kind and per kernel, with each kernel's
-    algorithmic GB/s against the HBM peak."""
-    import torch
-    import paper_1703_00640_amd as tm
-    from paper_1703_00640_amd import inputs
-    n = 1 << log2n
-    L = n // 64
-    dev = torch.device("cuda:0")
-    u, v = inputs.operand_pair(n, 5)
-    du = torch.from_numpy(u.view(np.int64)).to(dev)
-    dv = torch.from_numpy(v.view(np.int64)).to(dev)
-    del u, v
-    stream = torch.cuda.current_stream(dev)
-    res = {"n_bits": n, "ms": {}, "stage_ms": {}, "stage_gb_s": {}, "hbm_frac": {}, "plans": {}}
-    for k in ("lo", "hi", "full"):
-        pl = tm.autotune(k, n)
-        res["plans"][k] = {x: pl[x] for x in ("b", "lam", "N", "L1", "Lm", "L2")}
-        ws = torch.empty(pl["workspace_bytes"], dtype=torch.uint8, device=dev)
-        out = torch.empty(2 * L if k == "full" else L, dtype=torch.int64, device=dev)
-        for _ in range(2):
-            tm.mul(k, du, dv, n, out=out, workspace=ws, stream=stream)
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(steps):
-            tm.mul(k, du, dv, n, out=out, workspace=ws, stream=stream)
-        b.record(stream)
-        torch.cuda.synchronize()
-        res["ms"][k] = round(a.elapsed_time(b) / steps, 4)
-        acc = {}
-        for _ in range(steps):
-            for name, ms in tm.profile_stages(k, du, dv, n, out, ws, stream=stream):
-                acc.setdefault(name, []).append(ms)
-        nb = kernel_bytes(pl, n, k)
-        st = {name: float(np.median(vv)) for name, vv in acc.items()}
-        res["stage_ms"][k] = {nm: round(t, 4) for nm, t in st.items()}
-        res["stage_gb_s"][k] = {nm: round(nb[nm] / (t * 1e-3) / 1e9, 1) for nm, t in st.items()}
-        res["hbm_frac"][k] = {nm: round(nb[nm] / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 3) for nm, t in st.items()}
-        del ws, out
-        torch.cuda.empty_cache()
-    ceil = copy_ceiling_gb_s()
-    res["copy_ceiling_gb_s"] = ceil
-    res["copy_frac"] = {k: {nm: round(g / ceil, 3) for nm, g in v.items()} for k, v in res["stage_gb_s"].items()}
-    res["ratio_lo_full"] = round(res["ms"]["lo"] / res["ms"]["full"], 4)
-    res["ratio_hi_full"] = round(res["ms"]["hi"] / res["ms"]["full"], 4)
-    res["mbit_s"] = {k: round(n / (res["ms"][k] * 1e-3) / 1e6, 1) for k in res["ms"]}
-    return res
-
-
 def serving_bench(count=4096, n_streams=4):
     """Mixed-request serving through the continuous-batching server: count
     requests, n log-uniform over [2^12, 2^22] bits (whole limbs), kind
@@ -198,6 +152,9 @@ def serving_bench(count=4096, n_streams=4):
     # instance load its code; pinned staging buffers are allocated)
     serving.run(m, np.zeros(count), n_streams=n_streams)
     sat, _, _ = serving.run(m, np.zeros(count), n_streams=n_streams)
+    # every request arrives at t = 0 here: the spread of completion times is
+    # queueing, not latency, so only throughput is kept from this run
+    sat = {k: v for k, v in sat.items() if k not in ("p50_ms", "p99_ms")}
     out = {"workload": "%d requests, n log-uniform over [2^12, 2^22] bits, kind uniform "
                        "lo/hi/full, host operands (pinned), pool 1 GiB, %d streams"
                        % (count, n_streams),
@@ -355,9 +312,21 @@ def precision_bench(log2n=26, reps=5):
             os.environ.pop("TM_FORCE_B", None)
         else:
             os.environ["TM_FORCE_B"] = prev
-    b0 = tm.plan("hi", n)["b"]
-    adv = torch.from_numpy(inputs.digit_pattern(n, b0, 1 << (b0 - 1)).view(np.int64)).to(dev)
-    res["fp64_adversarial"] = measure(adv, adv)
+    # edge digits: every b-bit field of the high product's split (u 2^s,
+    # s = (N + 1) b - n) equal to 2^(b-1), so each balanced digit sits at
+    # the edge of its range; the default plan's guard reports it and the
+    # checked call recomputes with its guaranteed fallback
+    pl = tm.plan("hi", n)
+    b0, s0 = pl["b"], (pl["N"] + 1) * pl["b"] - n
+    adv = torch.from_numpy(inputs.digit_pattern(n, b0, 1 << (b0 - 1), s0).view(np.int64)).to(dev)
+    res["fp64_edge_digits"] = measure(adv, adv)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, gck = tm.mul_checked("hi", adv, adv, n)
+    res["fp64_edge_digits_checked"] = {"b": gck.b, "N": gck.N, "max_dist": round(gck.max_dist, 6),
+                                       "flags": gck.flags,
+                                       "ms_incl_sync": round((time.perf_counter() - t0) * 1e3, 3),
+                                       "fallback": "full product's guaranteed plan + extraction"}
     try:
         gp = tm.plan("hi", n, guaranteed=True)
         res["fp64_guaranteed"] = measure(du, dv, guaranteed=True)
@@ -368,32 +337,142 @@ def precision_bench(log2n=26, reps=5):
     return res
 
 
-def cpu_baseline(n_bits, threads):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n_bits, threads, n_single):
+    """The oracle (oracle/: schoolbook + Karatsuba on 64-bit limbs) timed on
+    the host cores: one full product of the benchmark's operand pair at
+    n_bits on `threads` threads (the oracle computes the low and high
+    products by extraction from the same full product, so its lo + hi + full
+    step is three of these), and one single-threaded full product at
+    n_single bits."""
     import oracle
     from paper_1703_00640_amd import inputs
-    u, v = inputs.operand_pair(n_bits, 2)
+    u, v = inputs.operand_pair(n_bits, 5)
     t0 = time.perf_counter()
-    oracle.mul_lo(u, v, n_bits, threads)
-    oracle.mul_hi(u, v, n_bits, threads)
     oracle.mul_full(u, v, n_bits, threads)
     dt = time.perf_counter() - t0
-    return {"value": round(3 * n_bits / dt / 1e6, 3), "unit": "operand Mbit/s",
-            "cores": threads, "kind": "oracle",
-            "sample": "one lo + hi + full product of one n=%d operand pair (%.1f s)" % (n_bits, dt)}
+    del u, v
+    u1, v1 = inputs.operand_pair(n_single, 2)
+    t1 = time.perf_counter()
+    oracle.mul_full(u1, v1, n_single, 1)
+    dt1 = time.perf_counter() - t1
+    return {"value": round(n_bits / dt / 1e6, 3), "unit": "operand Mbit/s",
+            "cores": threads, "kind": "oracle", "cpu": cpu_model(),
+            "sample": "one full product of the n=2^%d operand pair on %d threads (%.1f s); the "
+                      "oracle's lo+hi+full step is three such products"
+                      % (n_bits.bit_length() - 1, threads, dt),
+            "single_thread": {"n_bits": n_single, "seconds": round(dt1, 3),
+                              "value": round(n_single / dt1 / 1e6, 3)}}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def step_bench(tm, torch, n, steps, warmup, stage_reps, tag):
+    """Time one lo + hi + full step at n bits (autotuned splits), each kind
+    alone, squarings, and every kernel by HIP events on the launch stream.
+    Raises if any guard reports a flag."""
+    from paper_1703_00640_amd import inputs
+    L = n // 64
+    dev = torch.device("cuda:0")
+    u, v = inputs.operand_pair(n, tag)
+    du = torch.from_numpy(u.view(np.int64)).to(dev)
+    dv = torch.from_numpy(v.view(np.int64)).to(dev)
+    del u, v
+    kinds = ("lo", "hi", "full")
+    stream = torch.cuda.current_stream(dev)
+    plans = {k: tm.autotune(k, n, stream=stream) for k in kinds}
+    ws = {k: torch.empty(plans[k]["workspace_bytes"], dtype=torch.uint8, device=dev) for k in kinds}
+    outs = {k: torch.empty(2 * L if k == "full" else L, dtype=torch.int64, device=dev) for k in kinds}
+    guards = {k: tm.new_guard(dev) for k in kinds}
+
+    def one(k, a=du, b=dv):
+        tm.mul(k, a, b, n, out=outs[k], workspace=ws[k], stream=stream, guard=guards[k])
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    for _ in range(warmup):
+        for k in kinds:
+            one(k)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    ms_step = timed(lambda: [one(k) for k in kinds], steps)
+    wall = time.perf_counter() - t_wall
+    gd = {k: tm.read_guard(guards[k]).as_dict() for k in kinds}
+    per = {k: timed(lambda k=k: one(k), steps) for k in kinds}
+    per_sq = {k: timed(lambda k=k: one(k, du, du), steps) for k in kinds}
+    for k in kinds:
+        g = tm.read_guard(guards[k])
+        if g.flags or g.max_dist >= 0.25:
+            raise SystemExit("guard tripped at n=%d (%s): %s" % (n, k, g.as_dict()))
+    stage = {}
+    for k in kinds:
+        acc = {}
+        for _ in range(stage_reps):
+            for name, ms in tm.profile_stages(k, du, dv, n, outs[k], ws[k], stream=stream):
+                acc.setdefault(name, []).append(ms)
+        stage[k] = {name: float(np.median(vv)) for name, vv in acc.items()}
+    nbytes = {k: kernel_bytes(plans[k], n, k) for k in kinds}
+    res = {
+        "n_bits": n,
+        "ms_per_step": ms_step, "wall_s_timed": wall,
+        "plans": {k: {x: plans[k][x] for x in ("b", "lam", "N", "L1", "Lm", "L2", "via_full")}
+                  for k in kinds},
+        "ms": {k: round(per[k], 5) for k in kinds},
+        "mbit_s": {k: round(n / (per[k] * 1e-3) / 1e6, 1) for k in kinds},
+        "ratio_lo_full": round(per["lo"] / per["full"], 4),
+        "ratio_hi_full": round(per["hi"] / per["full"], 4),
+        "square_ms": {k: round(per_sq[k], 5) for k in kinds},
+        "stage_ms": {k: {s_: round(t, 5) for s_, t in stage[k].items()} for k in kinds},
+        "stage_gb_s": {k: {nm: round(nbytes[k][nm] / (t * 1e-3) / 1e9, 1) for nm, t in stage[k].items()}
+                       for k in kinds},
+        "hbm_frac": {k: {nm: round(nbytes[k][nm] / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)
+                         for nm, t in stage[k].items()} for k in kinds},
+        "guard_max_dist": {k: gd[k]["max_dist"] for k in kinds},
+        "guard_flags": {k: gd[k]["flags"] for k in kinds},
+    }
+    best = None
+    for k in kinds:
+        for name, ms in stage[k].items():
+            if best is None or ms > best[2]:
+                best = (k, name, ms, nbytes[k][name])
+    del ws, outs, du, dv
+    torch.cuda.empty_cache()
+    return res, best
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--log2n", type=int, default=24)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2n", type=int, default=30,
+                    help="operand size of the timed step (default 2^30, the largest single instance)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-log2n", type=int, default=28,
+                    help="operand size of the oracle's timed sample (a full product at 2^30 "
+                         "takes minutes on 16 cores; 2^28 keeps the run short)")
     ap.add_argument("--no-serve", action="store_true", help="skip the mixed-request serving runs")
-    ap.add_argument("--no-precision", action="store_true",
-                    help="skip the rounding-distance comparison at n = 2^26")
-    ap.add_argument("--large-log2n", type=int, default=30,
-                    help="also time the three products at n = 2^this (0: skip)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the n = 2^24 step, precision, small-n and mulmod sections")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="run the counter-collection workload instead of the benchmark")
     args = ap.parse_args()
@@ -407,90 +486,15 @@ def main():
 
     import torch
     import paper_1703_00640_amd as tm
-    from paper_1703_00640_amd import inputs
 
     n = 1 << args.log2n
-    L = n // 64
-    dev = torch.device("cuda:0")
-    u, v = inputs.operand_pair(n, 2)
-    du = torch.from_numpy(u.view(np.int64)).to(dev)
-    dv = torch.from_numpy(v.view(np.int64)).to(dev)
-    kinds = ("lo", "hi", "full")
-    # FFT split per kind from the library's autotuner (results unchanged)
-    plans = {k: tm.autotune(k, n) for k in kinds}
-    ws = {k: torch.empty(plans[k]["workspace_bytes"], dtype=torch.uint8, device=dev) for k in kinds}
-    outs = {k: torch.empty(2 * L if k == "full" else L, dtype=torch.int64, device=dev) for k in kinds}
-    guards = {k: tm.new_guard(dev) for k in kinds}
-    stream = torch.cuda.current_stream(dev)
-
-    def one(k):
-        tm.mul(k, du, dv, n, out=outs[k], workspace=ws[k], stream=stream, guard=guards[k])
-
-    for _ in range(args.warmup):
-        for k in kinds:
-            one(k)
-    torch.cuda.synchronize()
-
-    # whole step
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        for k in kinds:
-            one(k)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall
-    ms_step = e0.elapsed_time(e1) / args.steps
-
-    # per kind (separate timed loops, same stream)
-    per = {}
-    for k in kinds:
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(args.steps):
-            one(k)
-        b.record(stream)
-        torch.cuda.synchronize()
-        per[k] = a.elapsed_time(b) / args.steps
-
-    # squaring (u == v: one forward transform), same loop shape
-    per_sq = {}
-    for k in kinds:
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(args.steps):
-            tm.mul(k, du, du, n, out=outs[k], workspace=ws[k], stream=stream)
-        b.record(stream)
-        torch.cuda.synchronize()
-        per_sq[k] = a.elapsed_time(b) / args.steps
-
-    # per kernel, HIP events recorded by the library between its launches
-    stage = {k: {} for k in kinds}
-    reps = max(5, min(args.steps, 20))
-    for k in kinds:
-        acc = {}
-        for _ in range(reps):
-            for name, ms in tm.profile_stages(k, du, dv, n, outs[k], ws[k], stream=stream):
-                acc.setdefault(name, []).append(ms)
-        stage[k] = {name: float(np.mean(v)) for name, v in acc.items()}
-
-    best = None
-    for k in kinds:
-        nb = kernel_bytes(plans[k], n, k)
-        for name, ms in stage[k].items():
-            if best is None or ms > best[2]:
-                best = (k, name, ms, nb[name])
+    log("[bench] step at n=2^%d" % args.log2n)
+    head, best = step_bench(tm, torch, n, args.steps, args.warmup, 10, 5)
     k_dom, name_dom, ms_dom, bytes_dom = best
     achieved = bytes_dom / (ms_dom * 1e-3) / 1e9
     traffic = stored_traffic(args.log2n).get("%s:%s" % (k_dom, name_dom))
-    stage_gbs = {k: {nm: round(kernel_bytes(plans[k], n, k)[nm] / (t * 1e-3) / 1e9, 1)
-                     for nm, t in stage[k].items()} for k in kinds}
-
-    gd = {k: tm.read_guard(guards[k]).as_dict() for k in kinds}
+    ms_step = head.pop("ms_per_step")
+    wall = head.pop("wall_s_timed")
     result = {
         "metric": METRIC,
         "value": round(3 * n / (ms_step * 1e-3) / 1e6, 3),
@@ -503,40 +507,41 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic: uniform random limbs, PCG64 seeds 4 and 5",
-        "config": {"workload": "one mul_lo, mul_hi and mul_full of two n=2^%d-bit operands" % args.log2n,
-                   "n_bits": n, "limbs": L,
-                   "plans": {k: {x: plans[k][x] for x in ("b", "lam", "N", "L1", "Lm", "L2", "via_full")}
-                             for k in kinds}},
-        "ms": {k: round(per[k], 5) for k in kinds},
-        "mbit_s": {k: round(n / (per[k] * 1e-3) / 1e6, 2) for k in kinds},
-        "ratio_lo_full": round(per["lo"] / per["full"], 4),
-        "ratio_hi_full": round(per["hi"] / per["full"], 4),
-        "square_ms": {k: round(per_sq[k], 5) for k in kinds},
-        "stage_ms": {k: {s: round(t, 5) for s, t in stage[k].items()} for k in kinds},
-        "guard_max_dist": {k: gd[k]["max_dist"] for k in kinds},
-        "guard_flags": {k: gd[k]["flags"] for k in kinds},
+        "data": "synthetic: uniform random limbs, PCG64 streams 10 and 11",
+        "config": {"workload": "one mul_lo, mul_hi and mul_full of two n=2^%d-bit operands "
+                               "(largest single instance)" % args.log2n,
+                   "n_bits": n, "limbs": n // 64, "plans": head.pop("plans")},
         "roofline": {"bound": "hbm", "kernel": "%s:%s" % (k_dom, name_dom),
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": bytes_dom, "ms_per_launch": round(ms_dom, 5)},
-        "stage_gb_s": stage_gbs,
         "source_hash": source_hash(),
         "wall_s_timed": round(wall, 3),
     }
-    del ws, outs
-    torch.cuda.empty_cache()
-    if args.large_log2n:
-        result["large_n"] = large_n_bench(args.large_log2n, 5)
-    if not args.no_precision:
+    result.update(head)
+    log("[bench] copy ceiling")
+    ceil = copy_ceiling_gb_s()
+    result["copy_ceiling_gb_s"] = ceil
+    result["copy_frac"] = {k: {nm: round(g / ceil, 3) for nm, g in v.items()}
+                           for k, v in result["stage_gb_s"].items()}
+    if not args.no_extra:
+        log("[bench] step at n=2^24")
+        r24, _ = step_bench(tm, torch, 1 << 24, 50, 5, 20, 2)
+        r24["ms_per_step"] = round(r24["ms_per_step"], 5)
+        result["n2_24"] = r24
+        log("[bench] precision at n=2^26")
         result["precision"] = precision_bench()
+        log("[bench] small n")
         result["small_n"] = small_latency_bench()
+        log("[bench] mulmod")
         result["mulmod"] = mulmod_bench()
     if not args.no_serve:
+        log("[bench] serving")
         result["serving"] = serving_bench()
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
-        result["cpu_baseline"] = cpu_baseline(n, threads)
+        log("[bench] cpu oracle at n=2^%d on %d threads" % (args.cpu_log2n, threads))
+        result["cpu_baseline"] = cpu_baseline(1 << args.cpu_log2n, threads, 1 << 24)
     print(json.dumps(result), flush=True)
 
 

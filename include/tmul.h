@@ -58,8 +58,8 @@ typedef enum {
     TM_OK = 0,
     TM_ERR_INVALID = 1,     /* null pointer, n = 0, bad kind, workspace too small */
     TM_ERR_HIP = 2,         /* a HIP launch or runtime call failed               */
-    TM_ERR_PRECISION = 3,   /* tm_mul_checked: the rounding guard tripped even
-                               after the fallback plan                          */
+    TM_ERR_PRECISION = 3,   /* tm_mul_checked: the guaranteed fallback plan
+                               did not pass its own bound                       */
     TM_ERR_UNSUPPORTED = 4  /* n beyond the planner's limits                    */
 } tm_status;
 
@@ -141,7 +141,7 @@ tm_status tm_plan_query(tm_kind kind, uint64_t n_bits, tm_plan_info* out);
  * Low product: Algorithm "low product" (Section 3.4), with the ring maps of
  *   Propositions "approximating alpha*" and "approximating beta*" and the
  *   cancellation trick of Proposition "low-cancel".
- * High product: Algorithm "high product" (Section 4.4), with the maps of
+ * High product: Algorithm "high product" (Section 4.3), with the maps of
  *   Propositions "approximating gamma-dagger" / "approximating delta-dagger"
  *   and Proposition "high-cancel"; returns round(t), one of the at most two
  *   allowed values.
@@ -211,11 +211,19 @@ tm_status tm_mul_packed(const tm_request* reqs, size_t count, void* const* works
 
 /*
  * Like tm_mul, then synchronises the stream and reads the guard.  If it
- * tripped, recomputes with the fallback plan (the guaranteed plan when one
- * exists, else two bits smaller digits for the truncated products and four
- * for the full product; see tm_workspace_bytes_checked) and checks again.  *guard_host (may be NULL)
- * receives the guard of the last run.  Returns TM_ERR_PRECISION if the
- * fallback tripped too.
+ * tripped, recomputes with a fallback plan that is exact for every input by
+ * its worst-case rounding bound (see tm_mul_guaranteed): the guaranteed plan
+ * of the same kind when its digits are smaller, else, for the low and high
+ * products at sizes without a guaranteed truncated plan (beyond about 2^22
+ * bits), the full product's guaranteed plan followed by extraction of the
+ * requested bits.  A run of a guaranteed plan counts as exact when the guard
+ * reports only rounding distances within that plan's bound (below 1/2).
+ * The workspace must hold tm_workspace_bytes_checked() bytes (the larger of
+ * the two plans; at n = 2^30 the fallback needs about 4.3 GB).
+ * *guard_host (may be NULL) receives the guard of the last run.
+ * TM_ERR_PRECISION only if a guaranteed run reports a distance above its
+ * bound or another flag (a look-back spin limit), or if no fallback plan
+ * exists (the full product at sizes without a guaranteed plan).
  */
 size_t tm_workspace_bytes_checked(tm_kind kind, uint64_t n_bits);
 
@@ -225,7 +233,9 @@ size_t tm_workspace_bytes_checked(tm_kind kind, uint64_t n_bits);
  * (Section 5 chooses its parameters by testing).  With balanced digits
  * |U_i| <= 2^(b-1) and map gains 1 + 4 2^-b, the FFT convolution error is at
  * most ||G_u||_2 ||G_v||_2 ((1+u)^(3k) (1+sqrt5 u)^(3k+1) (1+t)^(3k) - 1),
- * u = 2^-53, t = 2^-49, k = ceil(lg M) + 4; scaled by 2^b for the truncated
+ * u = 2^-53, t = 2^-49, k = ceil(lg M) + 4 (the convolution error bound of
+ * Brent and Zimmermann, "Modern Computer Arithmetic", Theorem 3.6, which
+ * Section 2.1 cites for Convolution); scaled by 2^b for the truncated
  * products, plus 2^-8 of series truncation, it must stay below 0.45.  The
  * largest such b (at most the default) is used: every rounded coefficient is
  * then provably the nearest integer, for every input.  TM_ERR_UNSUPPORTED if

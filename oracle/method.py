@@ -331,18 +331,6 @@ def digit_product(U, V):
     return np.convolve(U.astype(object), V.astype(object))
 
 
-def digit_product_at(U, V, idx):
-    """w_k for selected k only (O(len) each), exact in Python ints."""
-    U = [int(t) for t in U]
-    V = [int(t) for t in V]
-    out = []
-    for k in idx:
-        lo = max(0, k - (len(V) - 1))
-        hi = min(k, len(U) - 1)
-        out.append(sum(U[j] * V[k - j] for j in range(lo, hi + 1)))
-    return out
-
-
 def low_coeffs_exact(W, N, b):
     """2^b L with L = W mod A written out as in the proof of the low
     cancellation proposition: L = sum_(i<N) w_i X^i

@@ -16,7 +16,12 @@
 
 namespace tmul {
 
-constexpr int B_TRUNC = 11;          // digit size of the truncated products (8..15)
+constexpr int B_TRUNC = 11;          // digit size of the truncated products
+// Every kind accepts digit sizes 8..16: the generic (runtime-b) K1 instances
+// size their staged digit windows for fields of at most 16 bits, K4 sizes
+// its per-thread limb arrays for b <= 16, and its limb carry needs b >= 8
+// (at most 9 coefficients start in one 64-bit limb).
+constexpr int B_MIN = 8, B_MAX = 16;
 constexpr int B_FULL = 16;           // digit size of the full product
 constexpr uint64_t TRUNC_MIN_BITS = 1025;  // below: full product + extraction
 constexpr uint32_t L2_MAX = 1024, L1_MAX = 4096, LM_MAX = 256;
@@ -125,9 +130,11 @@ inline uint64_t next_smooth(uint64_t x)
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Build the plan.  b_trunc / b_full: digit sizes (0 = default).
-// Returns false if unsupported.
-inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P, uint32_t force = 0)
+// Build the plan.  b_trunc / b_full: digit sizes (0 = default).  via_full:
+// serve a low or high product by the full product plus extraction at any n
+// (the checked entry point's last fallback).  Returns false if unsupported.
+inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P, uint32_t force = 0,
+                      bool via_full = false)
 {
     if (n == 0 || kind < 0 || kind > 2) return false;
     P = Plan();
@@ -136,8 +143,8 @@ inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P, ui
     P.L = (n + 63) / 64;
     const int bt = b_trunc ? b_trunc : B_TRUNC;
     const int bf = b_full ? b_full : B_FULL;
-    if (bt < 8 || bt > 15 || bf < 8 || bf > 16) return false;
-    P.via_full = kind != TM_FULL && n < TRUNC_MIN_BITS;
+    if (bt < B_MIN || bt > B_MAX || bf < B_MIN || bf > B_MAX) return false;
+    P.via_full = kind != TM_FULL && (n < TRUNC_MIN_BITS || via_full);
     P.kind = P.via_full ? TM_FULL : kind;
 
     if (P.kind == TM_FULL) {
@@ -208,8 +215,10 @@ inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P, ui
 //     add factors 1 + O(2^-b));
 //   * the FFT convolution differs from the exact one by at most
 //     ||G_u||_2 ||G_v||_2 eta, eta = (1+u)^(3k) (1+sqrt5 u)^(3k+1) (1+t)^(3k) - 1
-//     (the standard error bound of FFT-based convolution of length 2^k, unit
-//     roundoff u = 2^-53, twiddle error t), taken with k = ceil(lg M) + 4 to
+//     (the error bound of FFT-based convolution of length 2^k in Brent and
+//     Zimmermann, "Modern Computer Arithmetic", Theorem 3.6, the explicit
+//     bound Section 2.1 points to for Convolution; unit roundoff u = 2^-53,
+//     twiddle error t), taken with k = ceil(lg M) + 4 to
 //     cover the radix-3/16 codelets, the packed real transform, the
 //     inter-pass twiddles and the 1/M scaling, and t = 2^-49;
 //   * the truncated products scale by 2^b and the back map's gain g, and the
@@ -237,20 +246,31 @@ inline double rounding_bound(const Plan& P)
 constexpr double GUARANTEED_MAX = 0.45;
 
 // The guaranteed plan: the largest b (at most the default) whose bound is
-// below GUARANTEED_MAX; false if none with b >= 8 exists.
-inline bool make_plan_guaranteed(int kind, uint64_t n, Plan& P)
+// below GUARANTEED_MAX; false if none with b >= 8 exists.  via_full: the
+// full product's guaranteed plan serving a low or high product by
+// extraction (exists wherever the full product's does, n <= 2^30 and more).
+inline bool make_plan_guaranteed(int kind, uint64_t n, Plan& P, bool via_full = false)
 {
-    for (int b = B_FULL; b >= 8; b--) {
+    for (int b = B_FULL; b >= B_MIN; b--) {
         Plan Q;
-        const int bt = b <= 15 ? b : 0;  // truncated digit sizes stop at 15
-        if (kind != TM_FULL && b > B_TRUNC && n >= TRUNC_MIN_BITS) continue;
-        if (!make_plan(kind, n, bt, b, Q)) continue;
+        const bool trunc = kind != TM_FULL && !via_full && n >= TRUNC_MIN_BITS;
+        if (trunc && b > B_TRUNC) continue;
+        if (!make_plan(kind, n, b, b, Q, 0, via_full)) continue;
         if (rounding_bound(Q) <= GUARANTEED_MAX) {
             P = Q;
             return true;
         }
     }
     return false;
+}
+
+// A run of a plan whose worst-case bound is below 1/2 is exact when the
+// guard reports nothing but distances within that bound: every rounded
+// value then lies within the bound of its integer, so rounding returns it.
+inline bool exact_by_bound(const Plan& P, const tm_guard& g)
+{
+    const double bound = rounding_bound(P);
+    return bound <= GUARANTEED_MAX && (g.flags & ~TM_GUARD_DIST) == 0 && g.max_dist <= bound;
 }
 
 }  // namespace tmul

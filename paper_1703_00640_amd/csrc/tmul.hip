@@ -703,15 +703,16 @@ tm_status run_packed(const tm_request* reqs, size_t count, void* const* ws, cons
     return TM_OK;
 }
 
-// Fallback plan of tm_mul_checked: the guaranteed plan if there is one with
-// smaller digits, else two bits smaller digits for the truncated products
-// and four bits smaller for the full product.
+// Fallback plan of tm_mul_checked, exact for every input by its worst-case
+// bound: the guaranteed plan of the requested kind when it has smaller
+// digits than the plan that tripped, else (the truncated products beyond
+// the sizes where a guaranteed truncated plan exists) the full product's
+// guaranteed plan with extraction of the requested bits.
 bool fallback_plan(tm_kind kind, uint64_t n_bits, const Plan& P, Plan& F)
 {
     if (make_plan_guaranteed((int)kind, n_bits, F) && F.b < P.b) return true;
-    int bt = P.kind == TM_FULL ? 0 : P.b - 2;
-    int bf = P.kind == TM_FULL ? P.b - 4 : 0;
-    return make_plan((int)kind, n_bits, bt, bf, F);
+    if (kind == TM_FULL) return false;
+    return make_plan_guaranteed((int)kind, n_bits, F, true);
 }
 
 tm_status plan_guaranteed(tm_kind kind, uint64_t n, Plan& P)
@@ -1021,14 +1022,17 @@ tm_status tm_mul_checked(tm_kind kind, uint64_t* w, const uint64_t* u, const uin
                                hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         if (guard_host) *guard_host = g;
-        if (g.flags == 0) return TM_OK;
+        if (g.flags == 0 || exact_by_bound(P, g)) return TM_OK;
         if (attempt == 0) {
             Plan F;
-            if (!fallback_plan(kind, n_bits, P, F)) break;
+            if (!fallback_plan(kind, n_bits, P, F)) {
+                g_last_error = "rounding guard tripped and no guaranteed plan exists at this size";
+                return TM_ERR_PRECISION;
+            }
             P = F;
         }
     }
-    g_last_error = "rounding guard tripped after fallback";
+    g_last_error = "rounding guard tripped in the guaranteed fallback plan";
     return TM_ERR_PRECISION;
 }
 

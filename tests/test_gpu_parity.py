@@ -6,6 +6,8 @@ round(S / 2^D) with S from the exact closed-form coefficients (Prop.
 high-cancel).  Rounded coefficients are compared bit for bit with the closed
 forms; the unrounded ones with the FP64 model within a stated tolerance.
 """
+import hashlib
+import json
 import os
 import sys
 
@@ -185,20 +187,78 @@ def test_config_n2_24_parity():
 
 def test_large_b_truncated_trips_guard_and_checked_recovers(monkeypatch):
     """Negative control for the configs' literal b = 16 on the truncated
-    product: any b with 3b + lg N well above 53 fails in FP64.  Forced here
-    to b = 15 (the largest truncated digit size the kernels store); the guard
+    product: any b with 3b + lg N well above 53 fails in FP64.  The guard
     must trip, and the checked entry point must fall back to the guaranteed
     plan and return the right value."""
     tm = _tm()
     n = 1 << 16
     u, v = inputs.operand_pair(n, 3)
-    monkeypatch.setenv("TM_FORCE_B", "15")
+    monkeypatch.setenv("TM_FORCE_B", "16")
     lo, g = run_kind("lo", u, v, n)
-    say("  b=15 low product guard:", g.as_dict())
-    assert g.b == 15 and g.flags != 0
+    say("  b=16 low product guard:", g.as_dict())
+    assert g.b == 16 and g.flags != 0
     out, g2 = tm.mul_checked("lo", to_dev(u), to_dev(v), n)
     assert g2.flags == 0 and g2.b == tm.plan("lo", n, guaranteed=True)["b"]
     assert np.array_equal(to_host(out), oracle.mul_lo(u, v, n))
+
+
+def _edge_operand(tm, kind, n):
+    """Every b-bit digit of the plan equal to 2^(b-1): each balanced digit
+    sits at the edge of its range (Section 5 warns that such inputs break
+    parameters found on random inputs).  The high product splits u 2^s with
+    s = (N + 1) b - n, so its fields start s bits below bit 0."""
+    pl = tm.plan(kind, n)
+    shift = (pl["N"] + 1) * pl["b"] - n if (kind == "hi" and not pl["via_full"]) else 0
+    return inputs.digit_pattern(n, pl["b"], 1 << (pl["b"] - 1), shift)
+
+
+@pytest.mark.parametrize("log2n", [24, 26])
+def test_edge_digits_trip_guard_and_checked_is_exact(log2n):
+    """The edge-digit pattern of each kind's default plan at n = 2^24 and
+    2^26: the coefficients grow past what the statistical plan allows, so
+    tm_mul's guard must report it, and tm_mul_checked must return the
+    oracle's value through its guaranteed fallback (beyond 2^22 bits the
+    full product's guaranteed plan with extraction)."""
+    tm = _tm()
+    n = 1 << log2n
+    for kind in ("lo", "hi", "full"):
+        a = _edge_operand(tm, kind, n)
+        say("[edge] n=2^%d %s" % (log2n, kind))
+        w, g = run_kind(kind, a, a, n)
+        say("  default plan guard", g.as_dict())
+        assert g.flags != 0, "edge digits did not trip the guard (%s)" % kind
+        out, g2 = tm.mul_checked(kind, to_dev(a), to_dev(a), n)
+        got = to_host(out)
+        say("  checked guard", g2.as_dict())
+        # the guaranteed fallback ran: nothing but distances below 1/2
+        assert g2.b != g.b or g2.N != g.N
+        assert (g2.flags & ~1) == 0 and g2.max_dist < 0.5
+        if kind == "lo":
+            assert np.array_equal(got, oracle.mul_lo(a, a, n, 16))
+        elif kind == "full":
+            assert np.array_equal(got, oracle.mul_full(a, a, n, 16))
+        else:
+            q, nz = oracle.mul_hi(a, a, n, 16)
+            assert oracle.hi_accepts(got, q, nz)
+
+
+def test_checked_on_random_operands_keeps_default_plan():
+    """On uniform random operands the checked entry point returns after the
+    default plan (no fallback) with the oracle's values."""
+    tm = _tm()
+    n = (1 << 22) + 4160
+    u, v = inputs.operand_pair(n, 12)
+    for kind in ("lo", "hi", "full"):
+        out, g = tm.mul_checked(kind, to_dev(u), to_dev(v), n)
+        assert g.flags == 0 and g.b == tm.plan(kind, n)["b"]
+        got = to_host(out)
+        if kind == "lo":
+            assert np.array_equal(got, oracle.mul_lo(u, v, n, 16))
+        elif kind == "full":
+            assert np.array_equal(got, oracle.mul_full(u, v, n, 16))
+        else:
+            q, nz = oracle.mul_hi(u, v, n, 16)
+            assert oracle.hi_accepts(got, q, nz)
 
 
 @pytest.mark.parametrize("n", [1 << 16, 100003, 1 << 20])
@@ -372,24 +432,61 @@ def test_config_n2_26_parity():
     say("  guard lo %.4g hi %.4g full %.4g" % (glo.max_dist, ghi.max_dist, gfu.max_dist))
 
 
-def test_config_n2_30_residues_and_consistency():
-    """n = 2^30 (largest single instance): the full product checked modulo
-    three primes against the operands' residues (the oracle's residue
-    routine); the low product equals its low n bits and the high product is
-    one of the two allowed values derived from it."""
-    n = 1 << 30
-    L = n // 64
-    say("[parity] n=2^30")
-    u, v = inputs.operand_pair(n, 5)
-    full, gfu = run_kind("full", u, v, n)
-    for pmod in (2 ** 61 - 1, 2 ** 31 - 1, 1000000007):
-        assert oracle.residue(full, pmod) == oracle.residue(u, pmod) * oracle.residue(v, pmod) % pmod
-    lo, glo = run_kind("lo", u, v, n)
-    assert np.array_equal(lo, full[:L])
-    hi, ghi = run_kind("hi", u, v, n)
-    q = full[L:]
-    if not np.array_equal(hi, q):
-        assert np.any(full[:L] != 0) and oracle.to_int(hi) == oracle.to_int(q) + 1
-    for g in (glo, ghi, gfu):
-        assert g.flags == 0 and g.max_dist < 0.25, g.as_dict()
-    say("  guard lo %.4g hi %.4g full %.4g" % (glo.max_dist, ghi.max_dist, gfu.max_dist))
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<u8").tobytes()).hexdigest()
+
+
+def _check_large(tm, gold, du, dv, n, label):
+    """lo, hi, full at n = 2^30 against the oracle's digests: every limb of
+    the full and low products, and the high product equal to q or (when the
+    remainder is non-zero) q + 1."""
+    for kind in ("lo", "hi", "full"):
+        pl = tm.plan(kind, n)
+        split = (pl["L1"], pl["Lm"], pl["L2"])
+        g = tm.new_guard(dev())
+        w = to_host(tm.mul(kind, du, dv, n, guard=g))
+        gd = tm.read_guard(g)
+        say("[n=2^30 %s] %s split %s guard %.4g flags %d" % (label, kind, split, gd.max_dist, gd.flags))
+        assert gd.flags == 0 and gd.max_dist < 0.25, gd.as_dict()
+        h = _sha(w)
+        if kind == "full":
+            if h != gold["full_sha256"]:
+                bad = [(p, "%016x" % int(w[p]), x) for p, x in gold["full_samples"]
+                       if "%016x" % int(w[p]) != x]
+                pytest.fail("full product differs from the oracle (%s, split %s); sampled "
+                            "mismatches %s" % (label, split, bad[:8]))
+        elif kind == "lo":
+            assert h == gold["lo_sha256"], "low product differs (%s, split %s)" % (label, split)
+        else:
+            allowed = [gold["hi_q_sha256"]] + ([gold["hi_q_plus_1_sha256"]] if gold["hi_rem_nonzero"] else [])
+            assert h in allowed, "high product not in the allowed set (%s, split %s)" % (label, split)
+
+
+def test_config_n2_30_against_oracle(monkeypatch):
+    """n = 2^30 (largest single instance), element by element against the
+    oracle's product (its SHA-256 digests, written by
+    tests/golden/make_large_digests.py from oracle/ alone): the planner's
+    split, forced middle lengths Lm = 128 and 256 (the middle passes only
+    this size reaches), and the splits the autotuner picks for the
+    benchmark.  This size alone exercises the series length lambda = 7 of
+    the b = 11 maps."""
+    tm = _tm()
+    with open(os.path.join(GOLDEN, "large_products.json")) as f:
+        gold = json.load(f)
+    n = gold["n_bits"]
+    u, v = inputs.operand_pair(n, gold["tag"])
+    assert _sha(u) == gold["u_sha256"] and _sha(v) == gold["v_sha256"], "operand generator changed"
+    du, dv = to_dev(u), to_dev(v)
+    del u, v
+    assert tm.plan("lo", n)["lam"] == 7
+    _check_large(tm, gold, du, dv, n, "planner")
+    for lm in (128, 256):
+        monkeypatch.setenv("TM_FORCE_LM", str(lm))
+        _check_large(tm, gold, du, dv, n, "Lm=%d" % lm)
+    monkeypatch.delenv("TM_FORCE_LM")
+    for kind in ("lo", "hi", "full"):
+        tm.autotune(kind, n)
+    _check_large(tm, gold, du, dv, n, "autotuned")

@@ -214,3 +214,27 @@ def test_guaranteed_plans():
     # large n (the rounding guard covers them instead)
     assert tm.plan("lo", 1 << 24)["guaranteed"] == 0
     assert tm._load().tm_workspace_bytes_guaranteed(1, 1 << 24) == 0
+
+
+@pytest.mark.parametrize("log2n", [16, 20, 24, 26, 30])
+def test_checked_workspace_covers_an_exact_fallback(log2n):
+    """tm_mul_checked always has a fallback that is exact by its bound: the
+    guaranteed truncated plan where one exists (up to about 2^22 bits), else
+    the full product's guaranteed plan, whose workspace (two spectra of its
+    length) tm_workspace_bytes_checked must cover."""
+    import paper_1703_00640_amd as tm
+    n = 1 << log2n
+    gf = tm.plan("full", n, guaranteed=True)
+    assert gf["guaranteed"] == 1 and gf["rounding_bound"] <= 0.45
+    for kind in ("lo", "hi", "full"):
+        need = tm.workspace_bytes(kind, n, checked=True)
+        assert need >= tm.workspace_bytes(kind, n)
+        try:
+            g = tm.plan(kind, n, guaranteed=True)
+        except tm.TmulError:
+            g = None
+        if g is not None and (kind == "full" or g["b"] < tm.plan(kind, n)["b"]):
+            assert need >= g["workspace_bytes"]
+        else:
+            assert kind != "full" or g is None or g["b"] >= tm.plan(kind, n)["b"]
+            assert need >= 2 * gf["M"] * 16

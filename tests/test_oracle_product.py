@@ -125,6 +125,24 @@ def test_invariants_random():
         assert oracle.hi_accepts(q, q, nz)
 
 
+@pytest.mark.parametrize("L", [1, 2, 3, 17, 1000])
+def test_residue_against_python_int(L):
+    """residue(x, p) is x mod p by Python's own integer division, for random
+    limb arrays (top limbs with every bit pattern) and moduli of different
+    shapes: a Mersenne prime, a decimal prime, a tiny prime, an even number
+    and the largest allowed modulus."""
+    g = np.random.Generator(np.random.PCG64(4242 + L))
+    for trial in range(4):
+        x = g.integers(0, np.iinfo(np.uint64).max, size=L, dtype=np.uint64, endpoint=True)
+        if trial == 1:
+            x[-1] = np.uint64(0xFFFFFFFFFFFFFFFF)
+        if trial == 2:
+            x[:] = np.uint64(0xFFFFFFFFFFFFFFFF)
+        xi = oracle.to_int(x)
+        for p in (2 ** 61 - 1, 10 ** 9 + 7, 3, 2, 2 ** 62 + 6, 2 ** 63 - 25):
+            assert oracle.residue(x, p) == xi % p, (L, trial, p)
+
+
 def test_residue_check():
     n = 1 << 14
     u, v = inputs.operand_pair(n, 3)
