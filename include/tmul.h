@@ -35,7 +35,8 @@
  * - The library keeps one device-side cache per (device, transform length):
  *   the FFT twiddle tables, built on first use (this first call synchronises
  *   its stream once), and a few pinned host buffers for the launch metadata
- *   of packed batches.  tm_release_caches() frees them.
+ *   of packed batches.  tm_release_caches() waits for all work on the devices
+ *   holding tables (hipDeviceSynchronize) and frees them.
  */
 #ifndef TMUL_H
 #define TMUL_H

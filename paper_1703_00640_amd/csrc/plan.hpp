@@ -65,14 +65,39 @@ inline bool l1_supported(uint64_t x)
     return (y & (y - 1)) == 0;
 }
 
-// M = L1 * L2 with L2 = 2^lg near sqrt(M), or 2^force_lg when given
-inline bool split_M(uint64_t M, uint32_t& L1, uint32_t& L2, int force_lg = 0)
+// Row lengths with a K2 instance besides the powers of two 16..1024: the
+// odd factor 3 times a power of two (the truncated products' lengths
+// N = 3 2^a), so that the column pass can keep a power-of-two length.
+inline bool l2_supported(uint64_t x)
+{
+    if (x >= 16 && x <= 1024 && (x & (x - 1)) == 0) return true;
+    return x % 3 == 0 && x >= 96 && x <= 768 && ((x / 3) & (x / 3 - 1)) == 0;
+}
+
+// M = L1 * L2 with L2 = 2^lg near sqrt(M), or 2^force_lg when given.
+// odd_row: the odd factor of M goes to the row length instead, L2 = odd
+// 2^lg (lg: the largest that keeps L2 <= 1024, or force_lg), and L1 is a
+// power of two (no effect when M is a power of two).
+inline bool split_M(uint64_t M, uint32_t& L1, uint32_t& L2, int force_lg = 0, bool odd_row = false)
 {
     if (M < 32) return false;
     int a = 0;
     while (((M >> a) & 1) == 0) a++;
     uint64_t odd = M >> a;
     if (odd != 1 && odd != 3 && odd != 5 && odd != 7) return false;
+    if (odd_row && odd != 1) {
+        int lg = 0;
+        while ((odd << (lg + 1)) <= 1024 && lg + 1 <= a) lg++;
+        if (force_lg) {
+            if (force_lg < 4 || force_lg > lg) return false;
+            lg = force_lg;
+        }
+        const uint64_t l2 = odd << lg;
+        if (!l2_supported(l2) || M / l2 < 2) return false;
+        L2 = (uint32_t)l2;
+        L1 = (uint32_t)(M / l2);
+        return l1_supported(L1);
+    }
     int lg = (lg_ceil(M) + 1) / 2;
     if (lg < 4) lg = 4;
     if (lg > 10) lg = 10;
@@ -89,9 +114,14 @@ inline bool split_M(uint64_t M, uint32_t& L1, uint32_t& L2, int force_lg = 0)
 }
 
 // Forced FFT split (the autotuner's choice): low 16 bits the middle length
-// Lm (0: the planner's search, >= 1: exactly that Lm), high bits log2 of the
-// row length L2 (0: near sqrt).
-inline uint32_t split_code(uint32_t lm, int lg2) { return lm | ((uint32_t)lg2 << 16); }
+// Lm (0: the planner's search, >= 1: exactly that Lm), bits 16..23 log2 of
+// the power-of-two part of the row length L2 (0: the default), bit 24 the
+// odd factor of M in the row length rather than the column length.
+constexpr uint32_t SPLIT_ODD_ROW = 1u << 24;
+inline uint32_t split_code(uint32_t lm, int lg2, bool odd_row = false)
+{
+    return lm | ((uint32_t)lg2 << 16) | (odd_row ? SPLIT_ODD_ROW : 0u);
+}
 
 // M = L1 * Lm * L2: the smallest power of two Lm (the middle pass of the
 // three-pass split; 1 = two passes) that keeps the column length L1 <= 1024,
@@ -99,15 +129,16 @@ inline uint32_t split_code(uint32_t lm, int lg2) { return lm | ((uint32_t)lg2 <<
 inline bool split_M3(uint64_t M, uint32_t force, uint32_t& L1, uint32_t& Lm, uint32_t& L2)
 {
     const uint32_t force_lm = force & 0xffffu;
-    const int force_lg = (int)(force >> 16);
-    if (force_lm >= 1 && (force_lm > 1 || force_lg)) {
+    const int force_lg = (int)((force >> 16) & 0xffu);
+    const bool odd_row = (force & SPLIT_ODD_ROW) != 0;
+    if (force_lm >= 1 && (force_lm > 1 || force_lg || odd_row)) {
         Lm = force_lm;
-        return (Lm & (Lm - 1)) == 0 && Lm <= LM_MAX && M % Lm == 0 && split_M(M / Lm, L1, L2, force_lg) &&
-               L1 <= 1024;
+        return (Lm & (Lm - 1)) == 0 && Lm <= LM_MAX && M % Lm == 0 &&
+               split_M(M / Lm, L1, L2, force_lg, odd_row) && L1 <= 1024;
     }
     for (Lm = 1; Lm <= LM_MAX; Lm *= 2) {
         if (M % Lm != 0) return false;
-        if (split_M(M / Lm, L1, L2, force_lg) && L1 <= 1024) return true;
+        if (split_M(M / Lm, L1, L2, force_lg, odd_row) && L1 <= 1024) return true;
     }
     return false;
 }

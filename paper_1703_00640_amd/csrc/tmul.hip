@@ -93,7 +93,9 @@ std::map<std::tuple<int, uint64_t, uint32_t, uint32_t>, TwEntry> g_tw;
 
 // Twiddle tables for transform length M = L1 * Lm * L2, built once per
 // device and split (the sub-transform tables depend on L1, Lm and L2).
-tm_status get_twiddles(uint64_t M, uint32_t L1, uint32_t Lm, uint32_t L2, hipStream_t s, TwEntry& out)
+// build = false: look up only (callers that may not allocate).
+tm_status get_twiddles(uint64_t M, uint32_t L1, uint32_t Lm, uint32_t L2, hipStream_t s, TwEntry& out,
+                       bool build = true)
 {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -103,6 +105,10 @@ tm_status get_twiddles(uint64_t M, uint32_t L1, uint32_t Lm, uint32_t L2, hipStr
     if (it != g_tw.end()) {
         out = it->second;
         return TM_OK;
+    }
+    if (!build) {
+        g_last_error = "twiddle tables for this size are not built: call tm_prepare first";
+        return TM_ERR_INVALID;
     }
     // building a table allocates and synchronises: not allowed while the
     // stream is being captured into a graph (tm_prepare the size first)
@@ -166,6 +172,10 @@ bool launch_k2(uint32_t L2, const KParams& p, hipStream_t s)
     case 256: hipLaunchKernelGGL((k2_rows_pointwise<256>), g, dim3(NT2), 0, s, p); return true;
     case 512: hipLaunchKernelGGL((k2_rows_pointwise<512>), g, dim3(NT2), 0, s, p); return true;
     case 1024: hipLaunchKernelGGL((k2_rows_pointwise<1024>), g, dim3(NT2), 0, s, p); return true;
+    case 96: hipLaunchKernelGGL((k2_rows_pointwise<96>), g, dim3(NT2), 0, s, p); return true;
+    case 192: hipLaunchKernelGGL((k2_rows_pointwise<192>), g, dim3(NT2), 0, s, p); return true;
+    case 384: hipLaunchKernelGGL((k2_rows_pointwise<384>), g, dim3(NT2), 0, s, p); return true;
+    case 768: hipLaunchKernelGGL((k2_rows_pointwise<768>), g, dim3(NT2), 0, s, p); return true;
     }
     return false;
 }
@@ -222,7 +232,7 @@ bool launch_k2g(uint32_t L2, const Group& g, uint32_t blocks, hipStream_t s)
     switch (L2) {
 #define X(V) \
     case V: hipLaunchKernelGGL((k2_rows_pointwise_g<V>), dim3(blocks), dim3(NT2), 0, s, g); return true;
-        X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
+        X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(96) X(192) X(384) X(768)
 #undef X
     }
     return false;
@@ -504,10 +514,13 @@ tm_status plan_for(tm_kind kind, uint64_t n, Plan& P, int bt = 0, int bf = 0)
     uint32_t flm = 0;
     {
         // forced split (tests, experiments): middle length, log2 row length
+        // (of its power-of-two part), odd factor in the row length
         const char* e = getenv("TM_FORCE_LM");
         if (e && *e) flm = (uint32_t)atoi(e);
         const char* e2 = getenv("TM_FORCE_LG2");
         if (e2 && *e2) flm = split_code(flm, atoi(e2));
+        const char* e3 = getenv("TM_FORCE_ODD_ROW");
+        if (e3 && *e3 == '1') flm |= SPLIT_ODD_ROW;
     }
     if (!flm) flm = tuned_split(kind, n);
     if (!make_plan((int)kind, n, bt, bf, P, flm)) {
@@ -521,7 +534,7 @@ enum Mode { RUN, DIAG_RUN };
 
 tm_status run(const Plan& P, uint64_t* w, const uint64_t* u, const uint64_t* v, void* ws,
               size_t ws_bytes, hipStream_t s, tm_guard* guard, Mode mode, int64_t* dc,
-              double* dx, hipEvent_t* ev)
+              double* dx, hipEvent_t* ev, bool build_tables = true)
 {
     if (!u || !v || !ws || (mode == RUN && !w) || (mode == DIAG_RUN && !dc)) {
         g_last_error = "null pointer";
@@ -536,11 +549,9 @@ tm_status run(const Plan& P, uint64_t* w, const uint64_t* u, const uint64_t* v, 
         return TM_ERR_INVALID;
     }
     TwEntry tw;
-    tm_status st = get_twiddles(P.M, P.L1, P.Lm, P.L2, s, tw);
+    tm_status st = get_twiddles(P.M, P.L1, P.Lm, P.L2, s, tw, build_tables);
     if (st != TM_OK) return st;
     KParams p;
-    uint64_t dummy_out = 0;
-    (void)dummy_out;
     fill_params(P, u, v, w, ws, guard, tw, p);
     if (mode == DIAG_RUN) {
         // K1 clears out_limbs of w; point it at the coefficient buffer's
@@ -570,10 +581,16 @@ tm_status run(const Plan& P, uint64_t* w, const uint64_t* u, const uint64_t* v, 
     }
     if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
     if (P.Lm > 1) {
-        launch_mid<true>(p, s);
+        if (!launch_mid<true>(p, s)) {
+            g_last_error = "no kernel for Lm";
+            return TM_ERR_UNSUPPORTED;
+        }
         if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
     }
-    launch_k3(P.L1, p, s);
+    if (!launch_k3(P.L1, p, s)) {
+        g_last_error = "no kernel for L1";
+        return TM_ERR_UNSUPPORTED;
+    }
     if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
     if (mode == DIAG_RUN) launch_k4<true>(P.kind, p, s);
     else launch_k4<false>(P.kind, p, s);
@@ -781,24 +798,29 @@ tm_status tm_autotune(tm_kind kind, uint64_t n_bits, hipStream_t stream, tm_plan
     Plan P0;
     tm_status st = plan_for(kind, n_bits, P0);
     if (st != TM_OK) return st;
-    // candidates: the planner's split, every forced middle length, and for
-    // each middle length the row lengths twice and half the planner's
+    // candidates: the planner's split, every forced middle length with the
+    // odd factor of M in the column length or in the row length, and for
+    // each of these the row lengths twice and half its own
     std::vector<uint32_t> cand{0};
     std::vector<std::pair<uint32_t, uint32_t>> seen{{P0.Lm, P0.L2}};
     for (uint32_t lm = 1; lm <= LM_MAX; lm *= 2) {
-        Plan Q;
-        if (!make_plan((int)kind, n_bits, 0, 0, Q, split_code(lm, 0)) || Q.Lm != lm) continue;
-        const int lg = lg_ceil(Q.L2);
-        for (int lg2 : {0, lg + 1, lg - 1}) {
-            Plan S;
-            const uint32_t code = split_code(lm, lg2);
-            if (!make_plan((int)kind, n_bits, 0, 0, S, code)) continue;
-            const std::pair<uint32_t, uint32_t> key{S.Lm, S.L2};
-            bool dup = false;
-            for (auto& k : seen) dup = dup || k == key;
-            if (dup) continue;
-            seen.push_back(key);
-            cand.push_back(code);
+        for (bool odd_row : {false, true}) {
+            Plan Q;
+            if (!make_plan((int)kind, n_bits, 0, 0, Q, split_code(lm, 0, odd_row)) || Q.Lm != lm) continue;
+            uint32_t odd = Q.L2;
+            while (odd % 2 == 0) odd /= 2;
+            const int lg = lg_ceil(Q.L2 / odd);  // log2 of the row length's power-of-two part
+            for (int lg2 : {0, lg + 1, lg - 1}) {
+                Plan S;
+                const uint32_t code = split_code(lm, lg2, odd_row);
+                if (!make_plan((int)kind, n_bits, 0, 0, S, code)) continue;
+                const std::pair<uint32_t, uint32_t> key{S.Lm, S.L2};
+                bool dup = false;
+                for (auto& k : seen) dup = dup || k == key;
+                if (dup) continue;
+                seen.push_back(key);
+                cand.push_back(code);
+            }
         }
     }
     uint32_t best = 0;
@@ -1104,9 +1126,20 @@ const char* tm_last_error(void) { return g_last_error.c_str(); }
 void tm_release_caches(void)
 {
     {
+        // work still queued on any stream may read the tables: wait for
+        // each device that holds some before freeing them
         std::lock_guard<std::mutex> lk(g_tw_mu);
-        for (auto& kv : g_tw) (void)hipFree(kv.second.buf);
+        int cur = 0;
+        const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+        int last = -1;
+        for (auto& kv : g_tw) {
+            const int dev = std::get<0>(kv.first);
+            if (dev != last && hipSetDevice(dev) == hipSuccess) (void)hipDeviceSynchronize();
+            last = dev;
+            (void)hipFree(kv.second.buf);
+        }
         g_tw.clear();
+        if (have_cur) (void)hipSetDevice(cur);
     }
     std::lock_guard<std::mutex> lk(g_stage_mu);
     for (auto& kv : g_stage)

@@ -420,6 +420,32 @@ def test_every_row_length_keeps_products(monkeypatch, n):
     assert not bad, bad
 
 
+@pytest.mark.parametrize("n,lm", [(1 << 20, 0), ((1 << 22) + 4160, 0), (1 << 24, 0), (1 << 26, 0), (1 << 26, 64)])
+def test_odd_factor_in_rows(monkeypatch, n, lm):
+    """Splits with the odd factor of the transform length in the row length
+    (K2 rows of 3 2^a points, power-of-two columns), as the autotuner may
+    choose them: products equal the oracle's and the default split's."""
+    tm = _tm()
+    u, v = inputs.operand_pair(n, 93)
+    base = {k: run_kind(k, u, v, n, guard=False)[0] for k in ("lo", "hi")}
+    monkeypatch.setenv("TM_FORCE_ODD_ROW", "1")
+    if lm:
+        monkeypatch.setenv("TM_FORCE_LM", str(lm))
+    q, nz = oracle.mul_hi(u, v, n, 16)
+    want_lo = oracle.mul_lo(u, v, n, 16)
+    for k in ("lo", "hi"):
+        p = tm.plan(k, n)
+        say("[parity] odd row n=%d %s split %s" % (n, k, (p["L1"], p["Lm"], p["L2"])))
+        assert p["L2"] % 3 == 0 and p["L1"] & (p["L1"] - 1) == 0
+        w, g = run_kind(k, u, v, n)
+        assert g.flags == 0
+        assert np.array_equal(w, base[k])
+        if k == "lo":
+            assert np.array_equal(w, want_lo)
+        else:
+            assert oracle.hi_accepts(w, q, nz)
+
+
 def test_config_n2_26_parity():
     """n = 2^26 (three-pass split chosen automatically): lo, hi, full vs the
     oracle."""
@@ -486,6 +512,10 @@ def test_config_n2_30_against_oracle(monkeypatch):
     for lm in (128, 256):
         monkeypatch.setenv("TM_FORCE_LM", str(lm))
         _check_large(tm, gold, du, dv, n, "Lm=%d" % lm)
+    # the truncated products' odd factor in the rows (256 x 256 x 768)
+    monkeypatch.setenv("TM_FORCE_ODD_ROW", "1")
+    _check_large(tm, gold, du, dv, n, "Lm=256 odd row")
+    monkeypatch.delenv("TM_FORCE_ODD_ROW")
     monkeypatch.delenv("TM_FORCE_LM")
     for kind in ("lo", "hi", "full"):
         tm.autotune(kind, n)

@@ -238,3 +238,24 @@ def test_checked_workspace_covers_an_exact_fallback(log2n):
         else:
             assert kind != "full" or g is None or g["b"] >= tm.plan(kind, n)["b"]
             assert need >= 2 * gf["M"] * 16
+
+
+def test_odd_factor_in_rows_split(monkeypatch):
+    """Forcing the odd factor into the row length: at n = 2^30 with Lm = 256
+    the truncated products split 256 x 256 x 768 and the full product (a
+    power-of-two length) keeps its own split; lengths whose odd factor has no
+    row instance (5, 7) are refused."""
+    import paper_1703_00640_amd as tm
+    n = 1 << 30
+    monkeypatch.setenv("TM_FORCE_ODD_ROW", "1")
+    monkeypatch.setenv("TM_FORCE_LM", "256")
+    for kind in ("lo", "hi"):
+        p = tm.plan(kind, n)
+        assert (p["L1"], p["Lm"], p["L2"]) == (256, 256, 768)
+    p = tm.plan("full", n)
+    assert p["L1"] * p["Lm"] * p["L2"] == p["M"] and p["L2"] & (p["L2"] - 1) == 0
+    monkeypatch.delenv("TM_FORCE_LM")
+    p = tm.plan("lo", 1 << 20)
+    assert (p["L1"], p["Lm"], p["L2"]) == (64, 1, 768)
+    with pytest.raises(tm.TmulError):
+        tm.plan("lo", 3000000)  # N = 5 2^16
