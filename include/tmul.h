@@ -280,6 +280,26 @@ tm_status tm_profile_stages(tm_kind kind, uint64_t* w, const uint64_t* u, const 
                             int cap, int* n_stages);
 
 /*
+ * Allocation-free product, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same result as tm_mul (same plan and kernels) without a
+ * workspace argument: the workspace is a static device array of
+ * tm_noalloc_max_bytes() bytes (48 MiB: every kind up to n = 2^24 bits),
+ * one per GPU, held until the process ends.  The caller passes u, v, w and
+ * the stream as for tm_mul.  The size's twiddle tables must exist
+ * (tm_prepare, or an earlier tm_mul of the same size on this device):
+ * otherwise TM_ERR_INVALID and nothing runs.  TM_ERR_UNSUPPORTED if the
+ * plan's workspace exceeds the static maximum.  Calls no hipMalloc or
+ * hipFree.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (different streams or threads) race and give wrong
+ * results; each call starts by clearing what it accumulates into.
+ * guard_dev: device tm_guard or NULL (then the guard lives in the array).
+ */
+size_t tm_noalloc_max_bytes(void);
+tm_status tm_mul_noalloc(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v,
+                         uint64_t n_bits, hipStream_t stream, tm_guard* guard_dev);
+
+/*
  * Build the per-device caches a call of (kind, n_bits) uses (twiddle tables)
  * now, on `stream`, and wait for them.  Optional: every call builds them on
  * first use; servers call this before their clock starts.

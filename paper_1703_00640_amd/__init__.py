@@ -17,7 +17,7 @@ import torch
 __all__ = ["mul", "mul_lo", "mul_hi", "mul_full", "mul_batched", "mul_checked",
            "coefficients", "profile_stages", "plan", "workspace_bytes", "Guard",
            "TmulError", "KINDS", "library_path", "prepare", "Server", "serve_trace",
-           "server_footprint", "autotune", "mulmod"]
+           "server_footprint", "autotune", "mulmod", "mul_noalloc", "noalloc_max_bytes"]
 
 KINDS = {"full": 0, "lo": 1, "hi": 2}
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -89,6 +89,10 @@ def _load():
     lib.tm_mul_packed.argtypes = [P, SZ, P, P, P, SZ, P, P]
     lib.tm_mul_packed.restype = I32
     lib.tm_mul_checked.argtypes = [I32, P, P, P, U64, P, SZ, P, ctypes.POINTER(Guard)]
+    lib.tm_mul_noalloc.argtypes = [I32, P, P, P, U64, P, P]
+    lib.tm_mul_noalloc.restype = I32
+    lib.tm_noalloc_max_bytes.argtypes = []
+    lib.tm_noalloc_max_bytes.restype = SZ
     lib.tm_coefficients.argtypes = [I32, P, P, U64, P, P, U64, P, SZ, P, P]
     lib.tm_profile_stages.argtypes = [I32, P, P, P, U64, P, SZ, P,
                                       ctypes.POINTER(ctypes.c_float),
@@ -232,6 +236,25 @@ def mul(kind, u, v, n_bits, out=None, workspace=None, stream=None, guard=None,
     _check(f(k, pw, pu, pv, int(n_bits), ctypes.c_void_p(ws.data_ptr()),
              ws.numel() * ws.element_size(), _stream_ptr(stream, dev), g), "tm_mul")
     return out
+
+
+def mul_noalloc(kind, u, v, n_bits, out, stream=None, guard=None):
+    """tm_mul_noalloc: the product into the caller's ``out`` with the
+    library's static per-GPU scratch as workspace (no device allocation;
+    tm_prepare the size first).  Calls overlapping on one GPU race."""
+    k = _kind(kind)
+    L = nlimbs(n_bits)
+    dev = u.device
+    nout = 2 * L if k == 0 else L
+    g = ctypes.c_void_p(guard.data_ptr()) if guard is not None else None
+    _check(_load().tm_mul_noalloc(k, _dev_ptr(out, nout, "out"), _dev_ptr(u, L, "u"),
+                                  _dev_ptr(v, L, "v"), int(n_bits), _stream_ptr(stream, dev), g),
+           "tm_mul_noalloc")
+    return out
+
+
+def noalloc_max_bytes():
+    return _load().tm_noalloc_max_bytes()
 
 
 def mul_lo(u, v, n_bits, **kw):

@@ -15,6 +15,10 @@
 
 #include "tmul.h"
 #include "plan.hpp"
+
+#ifndef TM_NOALLOC_SCRATCH_BYTES
+#define TM_NOALLOC_SCRATCH_BYTES (48u << 20)
+#endif
 #include "kernels.hpp"
 #include "dispatch.hpp"
 
@@ -763,6 +767,39 @@ void fill_info(tm_kind kind, uint64_t n_bits, const Plan& P, tm_plan_info* out)
     out->guaranteed = out->rounding_bound <= GUARANTEED_MAX ? 1u : 0u;
 }
 
+// ------------------------------------------------------------ static scratch
+//
+// Workspace of tm_mul_noalloc: a file-scope device array, one copy per GPU,
+// held until the process ends.  In host code its name is a host-side
+// stand-in, not a device address: every host use goes through the address
+// hipGetSymbolAddress returns for the current device, taken once per device.
+constexpr size_t NOALLOC_MAX = TM_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) char scratch[NOALLOC_MAX];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch;
+
+tm_status scratch_ptr(void*& out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it != g_scratch.end()) {
+        out = it->second;
+        return TM_OK;
+    }
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255) != 0) {
+        g_last_error = "static scratch has no usable device address";
+        return TM_ERR_HIP;
+    }
+    g_scratch[dev] = ptr;
+    out = ptr;
+    return TM_OK;
+}
+
 }  // namespace
 
 // ================================================================ C ABI
@@ -930,6 +967,30 @@ tm_status tm_mul(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v
     if (st != TM_OK) return st;
     return run(P, w, u, v, workspace, workspace_bytes, stream, guard_dev, RUN, nullptr, nullptr,
                nullptr);
+}
+
+size_t tm_noalloc_max_bytes(void) { return NOALLOC_MAX; }
+
+tm_status tm_mul_noalloc(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v,
+                         uint64_t n_bits, hipStream_t stream, tm_guard* guard_dev)
+{
+    Plan P;
+    tm_status st = plan_for(kind, n_bits, P);
+    if (st != TM_OK) return st;
+    if (P.ws_bytes > NOALLOC_MAX) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "tm_mul_noalloc: needs %zu bytes of scratch, the static maximum is %zu",
+                 P.ws_bytes, NOALLOC_MAX);
+        g_last_error = buf;
+        return TM_ERR_UNSUPPORTED;
+    }
+    void* ws = nullptr;
+    st = scratch_ptr(ws);
+    if (st != TM_OK) return st;
+    // same kernels as tm_mul; K1 clears the look-back records, ticket and
+    // guard at the start of every call, so nothing carries over between calls
+    return run(P, w, u, v, ws, NOALLOC_MAX, stream, guard_dev, RUN, nullptr, nullptr, nullptr,
+               false);
 }
 
 tm_status tm_prepare(tm_kind kind, uint64_t n_bits, hipStream_t stream)
