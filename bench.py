@@ -467,9 +467,9 @@ def main():
     ap.add_argument("--log2n", type=int, default=30,
                     help="operand size of the timed step (default 2^30, the largest single instance)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-log2n", type=int, default=28,
-                    help="operand size of the oracle's timed sample (a full product at 2^30 "
-                         "takes minutes on 16 cores; 2^28 keeps the run short)")
+    ap.add_argument("--cpu-log2n", type=int, default=30,
+                    help="operand size of the oracle timing (the benchmark size by default; "
+                         "about a minute on 16 cores at 2^30)")
     ap.add_argument("--no-serve", action="store_true", help="skip the mixed-request serving runs")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the n = 2^24 step, precision, small-n and mulmod sections")

@@ -62,6 +62,10 @@ constexpr int DPT = TM_DPT;     // coefficients per thread in K4
 constexpr int NT4 = TM_NT4;     // threads per K4 workgroup
 constexpr int NT3 = TM_NT3;     // threads per K3 workgroup
 constexpr int DPW = DPT * NT4;  // coefficients per workgroup in K4
+#ifndef TM_K4_WAVES
+#define TM_K4_WAVES 8
+#endif
+constexpr int K4_WAVES = TM_K4_WAVES;  // K4 register bound: waves per SIMD
 #ifndef TM_TILE1
 #define TM_TILE1 4096
 #endif
@@ -998,21 +1002,6 @@ __device__ __forceinline__ uint64_t pack62(uint64_t state, int64_t v)
     return (state << 62) | ((uint64_t)v & ((1ull << 62) - 1));
 }
 __device__ __forceinline__ int64_t unpack62(uint64_t w) { return (int64_t)(w << 2) >> 2; }
-// poll a record word until its state is non-zero (bounded)
-__device__ __forceinline__ uint64_t poll_word(uint64_t* a, bool& timed_out)
-{
-    uint64_t w;
-    uint32_t spins = 0;
-    while (((w = ld_rlx(a)) >> 62) == 0) {
-        if (++spins > SPIN_LIMIT) {
-            timed_out = true;
-            return w;
-        }
-        __builtin_amdgcn_s_sleep(2);
-    }
-    return w;
-}
-
 __device__ __forceinline__ double wave_max(double v)
 {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
@@ -1370,23 +1359,48 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
             bool have_acc = false;
             int64_t e = (int64_t)g - 1;
             bool timed_out = false;
+            uint32_t spins = 0;
+            // Window of the 64 records below e, read without blocking.  A
+            // record absorbs when it fixes the carry by itself: an inclusive
+            // record, a constant aggregate, or the start of the number.  The
+            // window is usable as soon as the nearest absorbing record and
+            // every record between it and e are published: records further
+            // back cannot change the carry, so they are not waited for.
             while (true) {
                 const int64_t idx = e - 63 + lane;
-                bool incl = true;
+                bool ready = true, absorb = true;
                 CarryF fv = {0, INT64_MAX};  // before the number: carry 0
                 if (idx >= 0) {
-                    const uint64_t wa = poll_word(&st[2 * idx], timed_out);
-                    if ((wa >> 62) == 2) {
+                    const uint64_t wa = ld_rlx(&st[2 * idx]);
+                    const uint64_t sa = wa >> 62;
+                    if (sa == 2) {
                         fv.A = unpack62(wa);
-                    } else if ((wa >> 62) == 1) {
-                        const uint64_t wt = poll_word(&st[2 * idx + 1], timed_out);
-                        fv.A = unpack62(wa);
-                        fv.T = unpack62(wt);
-                        fv.T = fv.T <= V62_MIN ? INT64_MIN : fv.T >= V62_MAX ? INT64_MAX : fv.T;
-                        incl = false;
+                    } else if (sa == 1) {
+                        const uint64_t wt = ld_rlx(&st[2 * idx + 1]);
+                        if ((wt >> 62) == 0) {
+                            ready = absorb = false;
+                        } else {
+                            fv.A = unpack62(wa);
+                            fv.T = unpack62(wt);
+                            fv.T = fv.T <= V62_MIN ? INT64_MIN : fv.T >= V62_MAX ? INT64_MAX : fv.T;
+                            absorb = fv.T == INT64_MAX || fv.T == INT64_MIN;
+                        }
+                    } else {
+                        ready = absorb = false;
                     }
                 }
-                const bool any_incl = __ballot(incl) != 0;
+                const uint64_t mr = __ballot(ready), ma = __ballot(absorb);
+                const int top = ma ? 63 - __clzll((long long)ma) : 0;  // nearest absorbing lane
+                const uint64_t need = ~0ull << top;                      // lanes top .. 63
+                if ((mr & need) != need) {
+                    if (++spins > SPIN_LIMIT) {
+                        timed_out = true;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                    continue;
+                }
+                if (ma && lane < top) fv = CarryF{0, INT64_MAX};  // absorbed: any constant
                 // ordered reduction: lane 0 ends with f_(idx 63) o ... o f_(idx 0)
                 CarryF r = fv;
 #pragma unroll
@@ -1397,15 +1411,16 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
                 r.A = __shfl(r.A, 0);
                 r.T = __shfl(r.T, 0);
                 const CarryF tot = have_acc ? compose(r, acc) : r;
-                // done at an inclusive record, or as soon as the carry no
+                // done at an absorbing record, or as soon as the carry no
                 // longer depends on what lies further back (constant function)
-                if (any_incl || tot.T == INT64_MAX) {
+                if (ma || tot.T == INT64_MAX) {
                     cin = apply(tot, 0);
                     break;
                 }
                 acc = tot;
                 have_acc = true;
                 e -= 64;
+                spins = 0;
             }
             if (__ballot(timed_out) != 0 && lane == 0) atomicOr(&p.guard->flags, TM_GUARD_SPIN);
         }
@@ -1460,13 +1475,13 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
 // register bound this sets makes the high and full products' K4 about 12%
 // faster at n = 2^30
 template <int KIND, bool DIAG, int B>
-__global__ __launch_bounds__(NT4, 8) void k4_backmap_carry(KParams p)
+__global__ __launch_bounds__(NT4, K4_WAVES) void k4_backmap_carry(KParams p)
 {
     k4_body<KIND, DIAG, B>(p, blk_hw());
 }
 
 template <int KIND, int B>
-__global__ __launch_bounds__(NT4, 8) void k4_backmap_carry_g(Group g)
+__global__ __launch_bounds__(NT4, K4_WAVES) void k4_backmap_carry_g(Group g)
 {
     uint32_t pi;
     const Blk bk = group_block(g, pi);
