@@ -274,9 +274,10 @@ def mulmod_bench(log2n=24, reps=10):
 def precision_bench(log2n=26, reps=5):
     """The high product at n = 2^26 (the precision-comparison size): the
     maximum rounding distance over all coefficients (the guard) and the time
-    for digit sizes b = 10..13 on uniform random operands and for the
-    default b on the adversarial digit pattern (every digit 2^(b-1)), and
-    whether the worst-case bound admits a plan at this size."""
+    for FP64 digit sizes b = 10..13 on uniform random operands, for the
+    default b on the edge-digit pattern (every digit 2^(b-1)) with the
+    checked call's fallback, whether the worst-case bound admits a plan at
+    this size, and the FP32 path (double-float FFT passes, b = 9)."""
     import torch
     import paper_1703_00640_amd as tm
     from paper_1703_00640_amd import inputs
@@ -333,7 +334,25 @@ def precision_bench(log2n=26, reps=5):
         res["fp64_guaranteed"]["bound"] = gp["rounding_bound"]
     except tm.TmulError as e:
         res["fp64_guaranteed"] = {"supported": False, "reason": str(e)}
-    res["fp32_compensated"] = {"supported": False, "reason": "not built"}
+    # FP32 path: double-float FFT passes, digit sizes for its ~48-bit
+    # arithmetic (tm_mul_fp32c), random operands and the edge pattern of its
+    # own plan
+    g = tm.new_guard(dev)
+    out = tm.mul("hi", du, dv, n, guard=g, fp32c=True)
+    torch.cuda.synchronize()
+    gd = tm.read_guard(g)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        tm.mul("hi", du, dv, n, out=out, fp32c=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    pf = tm.plan("hi", n, fp32c=True)
+    res["fp32_compensated"] = {"b": gd.b, "lam": gd.lam, "N": gd.N, "max_dist": round(gd.max_dist, 6),
+                               "flags": gd.flags, "ms": round(e0.elapsed_time(e1) / reps, 4),
+                               "worst_case_bound": pf["rounding_bound"],
+                               "arithmetic": "double-float FFT passes; FP64 twiddle generation, "
+                                             "maps, theta, scaling, rounding"}
     return res
 
 

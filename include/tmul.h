@@ -252,6 +252,30 @@ tm_status tm_mul_checked(tm_kind kind, uint64_t* w, const uint64_t* u, const uin
                          hipStream_t stream, tm_guard* guard_host);
 
 /*
+ * FP32 path: the same three products with the FFT passes (column, middle
+ * and row passes, pointwise product) in double-float arithmetic, each real
+ * an unevaluated sum of two floats with error-free sums and FMA products
+ * (about 48 bits, the fixed-word-size scenario of Section 2.3 at a smaller
+ * working precision p).  FP64 is kept for twiddle generation (tables split
+ * into float pairs), the digits and ring maps, theta, the 2^b scaling, the
+ * rounding and the guard.  Digit sizes keep the FP64 plans' margin against
+ * the roundoff: b = 9 for the truncated products (their coefficient error
+ * grows as 2^(3b)) and b = 13 for the full product (2^(2b)); transform
+ * lengths are powers of two.  Same workspace layout, guard and conventions
+ * as tm_mul (tm_plan_query_fp32c reports the plan; tm_coefficients_fp32c is
+ * tm_coefficients for this path).
+ */
+size_t tm_workspace_bytes_fp32c(tm_kind kind, uint64_t n_bits);
+tm_status tm_plan_query_fp32c(tm_kind kind, uint64_t n_bits, tm_plan_info* out);
+tm_status tm_mul_fp32c(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v,
+                       uint64_t n_bits, void* workspace, size_t workspace_bytes,
+                       hipStream_t stream, tm_guard* guard_dev);
+tm_status tm_coefficients_fp32c(tm_kind kind, int64_t* coeffs, double* x, uint64_t coeffs_len,
+                                const uint64_t* u, const uint64_t* v, uint64_t n_bits,
+                                void* workspace, size_t workspace_bytes, hipStream_t stream,
+                                tm_guard* guard_dev);
+
+/*
  * Diagnostic: run the path up to rounding and write the rounded coefficients
  * c_i (int64, `coeffs_len` = plan.N for the full and low product, plan.N+1
  * for the high product) and the unrounded x_i (double, same length, may be

@@ -80,6 +80,14 @@ def _load():
     lib.tm_workspace_bytes_guaranteed.restype = SZ
     lib.tm_mul_guaranteed.argtypes = [I32, P, P, P, U64, P, SZ, P, P]
     lib.tm_mul_guaranteed.restype = I32
+    lib.tm_workspace_bytes_fp32c.argtypes = [I32, U64]
+    lib.tm_workspace_bytes_fp32c.restype = SZ
+    lib.tm_plan_query_fp32c.argtypes = [I32, U64, ctypes.POINTER(_PlanInfo)]
+    lib.tm_plan_query_fp32c.restype = I32
+    lib.tm_mul_fp32c.argtypes = [I32, P, P, P, U64, P, SZ, P, P]
+    lib.tm_mul_fp32c.restype = I32
+    lib.tm_coefficients_fp32c.argtypes = [I32, P, P, U64, P, P, U64, P, SZ, P, P]
+    lib.tm_coefficients_fp32c.restype = I32
     lib.tm_mul.argtypes = [I32, P, P, P, U64, P, SZ, P, P]
     for name in ("tm_mul_full", "tm_mul_lo", "tm_mul_hi"):
         getattr(lib, name).argtypes = [P, P, P, U64, P, SZ, P, P]
@@ -153,12 +161,14 @@ def nlimbs(n_bits):
     return (int(n_bits) + 63) // 64
 
 
-def plan(kind, n_bits, guaranteed=False):
+def plan(kind, n_bits, guaranteed=False, fp32c=False):
     """The plan (b, lambda, N, FFT split, workspace, rounding bound) used for
-    (kind, n_bits); guaranteed=True: the plan of tm_mul_guaranteed."""
+    (kind, n_bits); guaranteed=True: the plan of tm_mul_guaranteed;
+    fp32c=True: the plan of the FP32 path (tm_mul_fp32c)."""
     info = _PlanInfo()
     lib = _load()
-    f = lib.tm_plan_query_guaranteed if guaranteed else lib.tm_plan_query
+    f = lib.tm_plan_query_guaranteed if guaranteed else lib.tm_plan_query_fp32c if fp32c \
+        else lib.tm_plan_query
     _check(f(_kind(kind), int(n_bits), ctypes.byref(info)), "plan")
     return {k: getattr(info, k) for k, _ in _PlanInfo._fields_}
 
@@ -207,14 +217,16 @@ def read_guard(buf):
 
 
 def mul(kind, u, v, n_bits, out=None, workspace=None, stream=None, guard=None,
-        guaranteed=False):
+        guaranteed=False, fp32c=False):
     """w = product of ``kind`` ('lo', 'hi' or 'full') of u and v (n_bits each).
 
     Returns the output tensor (L limbs for lo/hi, 2L for full), enqueued on
     ``stream`` (default: torch's current stream).  ``guard`` may be a tensor
     from new_guard() to receive the rounding guard.  ``guaranteed``: use the
-    digit size of the worst-case rounding bound (tm_mul_guaranteed).  Passing
-    the same tensor as u and v computes a square with one forward transform."""
+    digit size of the worst-case rounding bound (tm_mul_guaranteed).
+    ``fp32c``: the FP32 path with double-float FFT passes (tm_mul_fp32c).
+    Passing the same tensor as u and v computes a square with one forward
+    transform."""
     k = _kind(kind)
     L = nlimbs(n_bits)
     dev = u.device
@@ -224,15 +236,17 @@ def mul(kind, u, v, n_bits, out=None, workspace=None, stream=None, guard=None,
         out = torch.empty(nout, dtype=torch.uint64, device=dev)
     pw = _dev_ptr(out, nout, "out")
     lib = _load()
-    if guaranteed:
-        nb = lib.tm_workspace_bytes_guaranteed(k, int(n_bits))
+    if guaranteed or fp32c:
+        nb = (lib.tm_workspace_bytes_guaranteed if guaranteed else lib.tm_workspace_bytes_fp32c)(
+            k, int(n_bits))
         if nb == 0:
-            raise TmulError("no guaranteed plan for (%s, %d)" % (kind, n_bits))
+            raise TmulError("no %s plan for (%s, %d)" % ("guaranteed" if guaranteed else "FP32",
+                                                        kind, n_bits))
     else:
         nb = workspace_bytes(k, n_bits)
     ws = _workspace(nb, dev, workspace)
     g = ctypes.c_void_p(guard.data_ptr()) if guard is not None else None
-    f = lib.tm_mul_guaranteed if guaranteed else lib.tm_mul
+    f = lib.tm_mul_guaranteed if guaranteed else lib.tm_mul_fp32c if fp32c else lib.tm_mul
     _check(f(k, pw, pu, pv, int(n_bits), ctypes.c_void_p(ws.data_ptr()),
              ws.numel() * ws.element_size(), _stream_ptr(stream, dev), g), "tm_mul")
     return out
@@ -315,23 +329,25 @@ def mul_checked(kind, u, v, n_bits, out=None, workspace=None, stream=None):
     return out, g
 
 
-def coefficients(kind, u, v, n_bits, with_x=True, workspace=None, stream=None):
+def coefficients(kind, u, v, n_bits, with_x=True, workspace=None, stream=None, fp32c=False):
     """Rounded coefficients c_i (int64) and unrounded x_i (float64) of the
-    plan for (kind, n_bits), plus the guard (synchronises)."""
+    plan for (kind, n_bits) (of the FP32 path with fp32c=True), plus the
+    guard (synchronises)."""
     k = _kind(kind)
     L = nlimbs(n_bits)
     dev = u.device
-    pl = plan(k, n_bits)
+    pl = plan(k, n_bits, fp32c=fp32c)
     ncoef = pl["N"] + (1 if (k == 2 and not pl["via_full"]) else 0)
     c = torch.empty(ncoef, dtype=torch.int64, device=dev)
     x = torch.empty(ncoef, dtype=torch.float64, device=dev) if with_x else None
-    ws = _workspace(workspace_bytes(k, n_bits), dev, workspace)
+    ws = _workspace(pl["workspace_bytes"], dev, workspace)
     gb = new_guard(dev)
-    _check(_load().tm_coefficients(k, ctypes.c_void_p(c.data_ptr()),
-                                   ctypes.c_void_p(x.data_ptr()) if x is not None else None,
-                                   ncoef, _dev_ptr(u, L, "u"), _dev_ptr(v, L, "v"), int(n_bits),
-                                   ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
-                                   _stream_ptr(stream, dev), ctypes.c_void_p(gb.data_ptr())),
+    f = _load().tm_coefficients_fp32c if fp32c else _load().tm_coefficients
+    _check(f(k, ctypes.c_void_p(c.data_ptr()),
+             ctypes.c_void_p(x.data_ptr()) if x is not None else None,
+             ncoef, _dev_ptr(u, L, "u"), _dev_ptr(v, L, "v"), int(n_bits),
+             ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+             _stream_ptr(stream, dev), ctypes.c_void_p(gb.data_ptr())),
            "tm_coefficients")
     torch.cuda.synchronize(dev)
     return c, x, read_guard(gb)

@@ -100,4 +100,13 @@ bool launch_k1g_full(uint32_t L1, int fb, bool wide, const Group& g, uint32_t bl
 bool launch_k1g_lo(uint32_t L1, int fb, bool wide, const Group& g, uint32_t blocks, hipStream_t s);
 bool launch_k1g_hi(uint32_t L1, int fb, bool wide, const Group& g, uint32_t blocks, hipStream_t s);
 
+// FP32 path (double-float FFT passes), defined in fp32c.hip
+bool launch_k1_fp32c(int kind, uint32_t L1, const KParams& p, hipStream_t s);
+bool launch_k2_fp32c(uint32_t L2, const KParams& p, hipStream_t s);
+template <bool INV>
+bool launch_mid_fp32c(const KParams& p, hipStream_t s);
+bool launch_k3_fp32c(uint32_t L1, const KParams& p, hipStream_t s);
+template <bool DIAG>
+bool launch_k4_fp32c(int kind, const KParams& p, hipStream_t s);
+
 }  // namespace tmul

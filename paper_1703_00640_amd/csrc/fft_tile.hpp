@@ -27,6 +27,7 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
     return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cneg(double2 a) { return make_double2(-a.x, -a.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 // multiply by -i (forward) or +i (inverse)
 template <bool INV>
@@ -44,24 +45,30 @@ __device__ __forceinline__ double2 tw_get(const Tw& t, uint32_t e)
     return INV ? cconj(w) : w;
 }
 
+}  // namespace tmul
+
+#include "dfloat.hpp"
+
+namespace tmul {
+
 // Twiddles base * step^q, q < Q, for a thread whose elements form an
 // arithmetic progression of exponents.  base and step are fetched from the
-// global table at kernel start (their latency hides behind the tile work);
-// powers use at most four products each.
-template <int Q>
+// global FP64 table at kernel start (their latency hides behind the tile
+// work); powers use at most four products each, in the tile's arithmetic C.
+template <int Q, typename C = double2>
 struct TwSeq {
-    double2 pw[4];
-    double2 base;
+    C pw[4];
+    C base;
     __device__ __forceinline__ void init(double2 b, double2 step)
     {
-        base = b;
-        pw[0] = step;
+        base = to_elem<C>(b);
+        pw[0] = to_elem<C>(step);
 #pragma unroll
         for (int i = 1; i < 4; i++) pw[i] = cmul(pw[i - 1], pw[i - 1]);
     }
-    __device__ __forceinline__ double2 at(int q) const
+    __device__ __forceinline__ C at(int q) const
     {
-        double2 w = base;
+        C w = base;
 #pragma unroll
         for (int i = 0; i < 4; i++)
             if ((1 << i) < Q && ((q >> i) & 1)) w = cmul(w, pw[i]);
@@ -238,8 +245,8 @@ __device__ __forceinline__ void dft16(double2* v)
     }
 }
 
-template <int R, bool INV>
-__device__ __forceinline__ void dftR(double2* v)
+template <int R, bool INV, typename C>
+__device__ __forceinline__ void dftR(C* v)
 {
     if constexpr (R == 2) dft2<INV>(v);
     else if constexpr (R == 3) dft3<INV>(v);
@@ -252,8 +259,8 @@ __device__ __forceinline__ void dftR(double2* v)
 
 // w^1 .. w^(R-1) from w: each power is one product of two earlier ones
 // (error grows with log2 r, not r)
-template <int R>
-__device__ __forceinline__ void tw_powers(double2 w, double2* pw)
+template <int R, typename C>
+__device__ __forceinline__ void tw_powers(C w, C* pw)
 {
     pw[1] = w;
 #pragma unroll
@@ -296,26 +303,26 @@ __device__ __forceinline__ int tile_addr(int j, int c)
 // LDS twiddle table length for a sub-transform of length P, and lookup of
 // exp(-2 pi i e / P), e < P.
 constexpr int twl_size(int P) { return P % 2 == 0 ? P / 2 : P; }
-template <int P>
-__device__ __forceinline__ double2 tw_half(const double2* twl, int e)
+template <int P, typename C>
+__device__ __forceinline__ C tw_half(const C* twl, int e)
 {
     if constexpr (P % 2 == 0) {
-        const double2 w = twl[e < P / 2 ? e : e - P / 2];
-        return e < P / 2 ? w : make_double2(-w.x, -w.y);
+        const C w = twl[e < P / 2 ? e : e - P / 2];
+        return e < P / 2 ? w : cneg(w);
     } else {
         return twl[e];
     }
 }
 
 // One Stockham stage of radix R after NS points have been combined.
-template <int P, int R, int NS, int NB, int NT, bool INV, bool COLS, int RS, int PS>
-__device__ __forceinline__ void fft_stage(double2* buf, const double2* twl)
+template <int P, int R, int NS, int NB, int NT, bool INV, bool COLS, int RS, int PS, typename C>
+__device__ __forceinline__ void fft_stage(C* buf, const C* twl)
 {
     constexpr int BF = P / R;
     constexpr int TOT = BF * NB;
     constexpr int PER = (TOT + NT - 1) / NT;
     constexpr uint32_t ESTEP = P / (NS * R);
-    double2 v[PER][R];
+    C v[PER][R];
     int jj[PER], cc[PER];
     const int tid = threadIdx.x;
 #pragma unroll
@@ -337,8 +344,8 @@ __device__ __forceinline__ void fft_stage(double2* buf, const double2* twl)
             const int k = (NS == 1) ? 0 : j % NS;
             if (NS > 1 && k != 0) {
                 // one table read per butterfly, the other twiddles as powers
-                const double2 w1 = tw_half<P>(twl, k * ESTEP);
-                double2 pw[R];
+                const C w1 = tw_half<P>(twl, k * ESTEP);
+                C pw[R];
                 tw_powers<R>(INV ? cconj(w1) : w1, pw);
 #pragma unroll
                 for (int r = 1; r < R; r++) v[q][r] = cmul(v[q][r], pw[r]);
@@ -352,8 +359,8 @@ __device__ __forceinline__ void fft_stage(double2* buf, const double2* twl)
     __syncthreads();
 }
 
-template <int P, int NS, int NB, int NT, bool INV, bool COLS, int RS, int PS>
-__device__ __forceinline__ void fft_stages(double2* buf, const double2* twl)
+template <int P, int NS, int NB, int NT, bool INV, bool COLS, int RS, int PS, typename C>
+__device__ __forceinline__ void fft_stages(C* buf, const C* twl)
 {
     if constexpr (NS < P) {
         constexpr int R = pick_radix(P / NS);
@@ -365,22 +372,22 @@ __device__ __forceinline__ void fft_stages(double2* buf, const double2* twl)
 // In-place DFT of NB sequences of length P in LDS; twl is an LDS table of
 // exp(-2 pi i e / P), e < P.  Caller must __syncthreads() before (data and
 // table written); the routine ends with a barrier.
-template <int P, int NB, int NT, bool INV, bool COLS, int RS = P, int PS = TM_PAD_SHIFT>
-__device__ __forceinline__ void tile_fft(double2* buf, const double2* twl)
+template <int P, int NB, int NT, bool INV, bool COLS, int RS = P, int PS = TM_PAD_SHIFT, typename C>
+__device__ __forceinline__ void tile_fft(C* buf, const C* twl)
 {
     fft_stages<P, 1, NB, NT, INV, COLS, RS, PS>(buf, twl);
 }
 
 // Copy the sub-transform table into LDS: the first half only when P is even
 // (exp(-2 pi i (e + P/2) / P) = -exp(-2 pi i e / P)).
-template <int P, int NT>
-__device__ __forceinline__ void load_twl(double2* twl, const double2* src)
+template <int P, int NT, typename C>
+__device__ __forceinline__ void load_twl(C* twl, const double2* src)
 {
     constexpr int H = twl_size(P);
 #pragma unroll
     for (int q = 0; q < (H + NT - 1) / NT; q++) {
         const int e = threadIdx.x + q * NT;
-        if (H % NT == 0 || e < H) twl[e] = src[e];
+        if (H % NT == 0 || e < H) twl[e] = to_elem<C>(src[e]);
     }
 }
 

@@ -512,7 +512,7 @@ __device__ __forceinline__ void row_map_edge(const KParams& p, uint32_t m0, doub
 // K1: split + map + column FFT for one column tile of the L1 x R matrix
 // (M = L1 R, R = Lm L2; element (k1, col) is point m = k1 R + col).
 // B: compile-time digit size (0: runtime p.b).
-template <int L1, int W, int KIND, int B>
+template <int L1, int W, int KIND, int B, typename C = double2>
 __device__ __forceinline__ void k1_body(const KParams& p, const Blk bk)
 {
     static_assert(L1 * W <= TILE1, "tile too large");
@@ -526,12 +526,12 @@ __device__ __forceinline__ void k1_body(const KParams& p, const Blk bk)
     constexpr bool STAGE = L1 * NLWP * 8 <= TE * 16;
     static_assert(STAGE || B == 0, "compile-time digit sizes need staged limbs");
     constexpr int RPT = (L1 + NT1 - 1) / NT1;
-    __shared__ double2 tile[TE];
-    __shared__ double2 twl[twl_size(L1)];
+    __shared__ C tile[TE];
+    __shared__ C twl[twl_size(L1)];
     __shared__ double s_th[LMAX + 8];  // terms of theta (high product, tile 0)
     const int op = bk.y;
     const uint64_t* x = op ? p.v : p.u;
-    double2* dst = op ? p.zb : p.za;
+    C* dst = reinterpret_cast<C*>(op ? p.zb : p.za);
     const uint32_t L2 = p.R;  // row length of the L1 x R matrix
     const uint32_t c0 = xcd_tile(bk.x, bk.nx) * W;
     const int tid = threadIdx.x;
@@ -629,12 +629,12 @@ __device__ __forceinline__ void k1_body(const KParams& p, const Blk bk)
         const int j1 = tid + rr * NT1;
         if (L1 % NT1 == 0 || j1 < L1) {
 #pragma unroll
-            for (int c = 0; c < W; c++) tile[pidx(j1 * W + c)] = g[rr][c];
+            for (int c = 0; c < W; c++) tile[pidx(j1 * W + c)] = to_elem<C>(g[rr][c]);
         }
     }
     __syncthreads();
     tile_fft<L1, W, NT1, false, true>(tile, twl);
-    TwSeq<PER> tws;
+    TwSeq<PER, C> tws;
     tws.init(cmul(tb0, tb1), cmul(ts0, ts1));
 #pragma unroll
     for (int q = 0; q < PER; q++) {
@@ -646,10 +646,10 @@ __device__ __forceinline__ void k1_body(const KParams& p, const Blk bk)
     }
 }
 
-template <int L1, int W, int KIND, int B>
+template <int L1, int W, int KIND, int B, typename C = double2>
 __global__ __launch_bounds__(NT1) void k1_split_map_col(KParams p)
 {
-    k1_body<L1, W, KIND, B>(p, blk_hw());
+    k1_body<L1, W, KIND, B, C>(p, blk_hw());
 }
 
 template <int L1, int W, int KIND, int B>
@@ -670,18 +670,18 @@ __global__ __launch_bounds__(NT1) void k1_split_map_col_g(Group g)
 // and odd parts are E'_k = Ea Eb + w^k Oa Ob and O'_k = Ea Ob + Oa Eb with
 // w = exp(-2 pi i / M), and Q_k = E'_k + i O'_k is the length-M transform of
 // (W_2m + i W_2m+1) (times M).
-__device__ __forceinline__ double2 pointwise_bin(double2 Ya, double2 Yam, double2 Yb, double2 Ybm,
-                                                 double2 wk)
+template <typename C>
+__device__ __forceinline__ C pointwise_bin(C Ya, C Yam, C Yb, C Ybm, C wk)
 {
-    double2 Ea = cscale(cadd(Ya, cconj(Yam)), 0.5);
-    double2 Oa = cscale(csub(Ya, cconj(Yam)), 0.5);
-    Oa = make_double2(Oa.y, -Oa.x);  // divide by i
-    double2 Eb = cscale(cadd(Yb, cconj(Ybm)), 0.5);
-    double2 Ob = cscale(csub(Yb, cconj(Ybm)), 0.5);
-    Ob = make_double2(Ob.y, -Ob.x);
-    double2 X = cadd(cmul(Ea, Eb), cmul(wk, cmul(Oa, Ob)));
-    double2 Yv = cadd(cmul(Ea, Ob), cmul(Oa, Eb));
-    return make_double2(X.x - Yv.y, X.y + Yv.x);  // X + i Yv
+    C Ea = cscale(cadd(Ya, cconj(Yam)), 0.5);
+    C Oa = cscale(csub(Ya, cconj(Yam)), 0.5);
+    Oa = mul_mi<false>(Oa);  // divide by i
+    C Eb = cscale(cadd(Yb, cconj(Ybm)), 0.5);
+    C Ob = cscale(csub(Yb, cconj(Ybm)), 0.5);
+    Ob = mul_mi<false>(Ob);
+    C X = cadd(cmul(Ea, Eb), cmul(wk, cmul(Oa, Ob)));
+    C Yv = cadd(cmul(Ea, Ob), cmul(Oa, Eb));
+    return cadd(X, mul_mi<true>(Yv));  // X + i Yv
 }
 
 // Row pairs of K2.  Row (k1, km) (k1 < L1, km < Lm) holds bins
@@ -748,12 +748,14 @@ __device__ __forceinline__ K2Rows k2_rows_of(uint32_t g, uint32_t L1, uint32_t L
     return r;
 }
 
-template <int L2>
+template <int L2, typename C = double2>
 __device__ __forceinline__ void k2_body(const KParams& p, const Blk bk)
 {
     // rows 0,1: operands u,v at row (k1, km); rows 2,3: at the mirror row
-    __shared__ double2 rows[padded<PAD2>(4 * L2)];
-    __shared__ double2 twl[twl_size(L2)];
+    __shared__ C rows[padded<PAD2>(4 * L2)];
+    __shared__ C twl[twl_size(L2)];
+    C* za = reinterpret_cast<C*>(p.za);
+    const C* zb = reinterpret_cast<const C*>(p.zb);
     const uint32_t L1 = p.L1, Lm = p.Lm;
     const K2Rows rr = k2_rows_of(bk.x, L1, Lm);
     const uint32_t rowa = rr.rowa, rowb = rr.rowb;
@@ -765,14 +767,14 @@ __device__ __forceinline__ void k2_body(const KParams& p, const Blk bk)
     const double2 wr1a = p.tw.lo[rhob & p.tw.mask], wr1b = p.tw.hi[rhob >> p.tw.shift];
     {
         constexpr int PL = (4 * L2 + NT2 - 1) / NT2;
-        double2 v[PL];
+        C v[PL];
 #pragma unroll
         for (int q = 0; q < PL; q++) {
             const int e = threadIdx.x + q * NT2;
             if (4 * L2 % NT2 == 0 || e < 4 * L2) {
                 const int r = e / L2, j2 = e % L2;
                 const uint32_t row = r < 2 ? rowa : rowb;
-                const double2* src = (r & 1) ? p.zb : p.za;
+                const C* src = (r & 1) ? zb : za;
                 v[q] = src[(size_t)row * L2 + j2];
             }
         }
@@ -786,8 +788,8 @@ __device__ __forceinline__ void k2_body(const KParams& p, const Blk bk)
     tile_fft<L2, 4, NT2, false, false, L2, PAD2>(rows, twl);
 
     constexpr int PER = (2 * L2 + NT2 - 1) / NT2;
-    const double2 wrow0 = cmul(wr0a, wr0b), wrow1 = cmul(wr1a, wr1b);
-    double2 qv[PER];
+    const C wrow0 = to_elem<C>(cmul(wr0a, wr0b)), wrow1 = to_elem<C>(cmul(wr1a, wr1b));
+    C qv[PER];
 #pragma unroll
     for (int t = 0; t < PER; t++) {
         const int e = threadIdx.x + t * NT2;
@@ -817,16 +819,16 @@ __device__ __forceinline__ void k2_body(const KParams& p, const Blk bk)
     for (int e = threadIdx.x; e < 2 * L2; e += NT2) {
         const int pr = e / L2, j2 = e % L2;
         if (pr == 1 && rowb == rowa) continue;
-        p.za[(size_t)(pr ? rowb : rowa) * L2 + j2] = rows[pidx<PAD2>((2 * pr) * L2 + j2)];
+        za[(size_t)(pr ? rowb : rowa) * L2 + j2] = rows[pidx<PAD2>((2 * pr) * L2 + j2)];
     }
 }
 
 // rows of up to 512 points fit four workgroups per CU in LDS; the second
 // bound (waves per SIMD) keeps their registers within that occupancy
-template <int L2>
+template <int L2, typename C = double2>
 __global__ __launch_bounds__(NT2, L2 <= 512 ? 4 : 2) void k2_rows_pointwise(KParams p)
 {
-    k2_body<L2>(p, blk_hw());
+    k2_body<L2, C>(p, blk_hw());
 }
 
 template <int L2>
@@ -845,16 +847,16 @@ __global__ __launch_bounds__(NT2, L2 <= 512 ? 4 : 2) void k2_rows_pointwise_g(Gr
 // adjacent columns j2.  Forward: DFT, then exp(-2 pi i j2 km / R), in place
 // on both operands.  Inverse: exp(+2 pi i j2 km / R), then inverse DFT, on
 // the product.  grid = (L2 / W, L1, operands).
-template <int LM, int W, bool INV>
+template <int LM, int W, bool INV, typename C = double2>
 __device__ __forceinline__ void mid_body(const KParams& p, const Blk bk)
 {
     constexpr int PER = (LM * W + NTM - 1) / NTM;
     static_assert(NTM % W == 0, "W must divide NTM");
-    __shared__ double2 tile[padded(LM * W)];
-    __shared__ double2 twl[twl_size(LM)];
+    __shared__ C tile[padded(LM * W)];
+    __shared__ C twl[twl_size(LM)];
     const uint32_t L2 = p.L2;
     const uint32_t c0 = xcd_tile(bk.x, bk.nx) * W;
-    double2* a = (bk.z ? p.zb : p.za) + (size_t)bk.y * p.R;
+    C* a = reinterpret_cast<C*>(bk.z ? p.zb : p.za) + (size_t)bk.y * p.R;
     const int tid = threadIdx.x;
     load_twl<LM, NTM>(twl, p.twm);
     // twiddle exponents on the R-th root, as exponents of the M-th root (x L1)
@@ -863,13 +865,13 @@ __device__ __forceinline__ void mid_body(const KParams& p, const Blk bk)
     const uint32_t es = (uint32_t)(((uint64_t)colt * (uint32_t)(NTM / W) * p.L1) % p.M);
     const double2 tb0 = p.tw.lo[eb & p.tw.mask], tb1 = p.tw.hi[eb >> p.tw.shift];
     const double2 ts0 = p.tw.lo[es & p.tw.mask], ts1 = p.tw.hi[es >> p.tw.shift];
-    double2 v[PER];
+    C v[PER];
 #pragma unroll
     for (int q = 0; q < PER; q++) {
         const int e = tid + q * NTM;
         if (LM * W % NTM == 0 || e < LM * W) v[q] = a[(size_t)(e / W) * L2 + colt];
     }
-    TwSeq<PER> tws;
+    TwSeq<PER, C> tws;
     if (INV) tws.init(cconj(cmul(tb0, tb1)), cconj(cmul(ts0, ts1)));
     else tws.init(cmul(tb0, tb1), cmul(ts0, ts1));
 #pragma unroll
@@ -883,16 +885,16 @@ __device__ __forceinline__ void mid_body(const KParams& p, const Blk bk)
     for (int q = 0; q < PER; q++) {
         const int e = tid + q * NTM;
         if (LM * W % NTM == 0 || e < LM * W) {
-            const double2 t = tile[pidx(e)];
+            const C t = tile[pidx(e)];
             a[(size_t)(e / W) * L2 + colt] = INV ? t : cmul(t, tws.at(q));
         }
     }
 }
 
-template <int LM, int W, bool INV>
+template <int LM, int W, bool INV, typename C = double2>
 __global__ __launch_bounds__(NTM) void k_mid_col(KParams p)
 {
-    mid_body<LM, W, INV>(p, blk_hw());
+    mid_body<LM, W, INV, C>(p, blk_hw());
 }
 
 template <int LM, int W, bool INV>
@@ -906,11 +908,12 @@ __global__ __launch_bounds__(NTM) void k_mid_col_g(Group g)
 
 // ------------------------------------------------------------------- K3
 
-template <int L1, int W>
+template <int L1, int W, typename C = double2>
 __device__ __forceinline__ void k3_body(const KParams& p, const Blk bk)
 {
-    __shared__ double2 tile[padded(L1 * W)];
-    __shared__ double2 twl[twl_size(L1)];
+    __shared__ C tile[padded(L1 * W)];
+    __shared__ C twl[twl_size(L1)];
+    C* za = reinterpret_cast<C*>(p.za);
     const uint32_t L2 = p.R;  // row length of the L1 x R matrix
     const uint32_t c0 = xcd_tile(bk.x, bk.nx) * W;
     load_twl<L1, NT3>(twl, p.tw1);
@@ -923,14 +926,14 @@ __device__ __forceinline__ void k3_body(const KParams& p, const Blk bk)
     const double2 tb0 = p.tw.lo[eb & p.tw.mask], tb1 = p.tw.hi[eb >> p.tw.shift];
     const double2 ts0 = p.tw.lo[es & p.tw.mask], ts1 = p.tw.hi[es >> p.tw.shift];
     {
-        double2 v[PER];
+        C v[PER];
 #pragma unroll
         for (int q = 0; q < PER; q++) {
             const int e = tid + q * NT3;
-            if (L1 * W % NT3 == 0 || e < L1 * W) v[q] = p.za[(size_t)(e / W) * L2 + colt];
+            if (L1 * W % NT3 == 0 || e < L1 * W) v[q] = za[(size_t)(e / W) * L2 + colt];
         }
         // inverse inter-pass twiddles exp(+2 pi i col k1 / M)
-        TwSeq<PER> tws;
+        TwSeq<PER, C> tws;
         tws.init(cconj(cmul(tb0, tb1)), cconj(cmul(ts0, ts1)));
 #pragma unroll
         for (int q = 0; q < PER; q++) {
@@ -943,14 +946,14 @@ __device__ __forceinline__ void k3_body(const KParams& p, const Blk bk)
 #pragma unroll
     for (int q = 0; q < PER; q++) {
         const int e = threadIdx.x + q * NT3;
-        if (L1 * W % NT3 == 0 || e < L1 * W) p.za[(size_t)(e / W) * L2 + c0 + e % W] = tile[pidx(e)];
+        if (L1 * W % NT3 == 0 || e < L1 * W) za[(size_t)(e / W) * L2 + c0 + e % W] = tile[pidx(e)];
     }
 }
 
-template <int L1, int W>
+template <int L1, int W, typename C = double2>
 __global__ __launch_bounds__(NT3) void k3_col_inverse(KParams p)
 {
-    k3_body<L1, W>(p, blk_hw());
+    k3_body<L1, W, C>(p, blk_hw());
 }
 
 template <int L1, int W>
@@ -1108,7 +1111,19 @@ __device__ __forceinline__ void back_chain(const KParams& p, const double* sq, i
     }
 }
 
-template <int KIND, bool DIAG, int B>
+// Real element i of the packed convolution result (real parts at even i,
+// imaginary parts at odd i), in FP64.
+__device__ __forceinline__ double real_at(const double2* z, int64_t i)
+{
+    return reinterpret_cast<const double*>(z)[i];
+}
+__device__ __forceinline__ double real_at(const dfc* z, int64_t i)
+{
+    const dfc c = z[i >> 1];
+    return df_to((i & 1) ? c.y : c.x);
+}
+
+template <int KIND, bool DIAG, int B, typename C = double2>
 __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
 {
     constexpr int NW = NT4 / 64;
@@ -1123,7 +1138,7 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
     __shared__ double s_edge[K4_HALO + 1];
     __shared__ double sc_edge[K4_HALO * K4_EP];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const double* q = reinterpret_cast<const double*>(p.za);
+    const C* q = reinterpret_cast<const C*>(p.za);
 
     if (tid == 0) {
         s_g = DIAG ? bk.x : atomicAdd(p.ticket, 1u);
@@ -1141,7 +1156,7 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
     for (int e = tid; e < DPW + K4_HALO; e += NT4) {
         int64_t i = (int64_t)base - K4_HALO + e;
         if (i < 0 && KIND != K_FULL) i += p.N;  // cyclic: wrapped terms of the maps
-        sq[padq(e)] = (i >= 0 && i < (int64_t)p.N) ? q[i] : 0.0;
+        sq[padq(e)] = (i >= 0 && i < (int64_t)p.N) ? real_at(q, i) : 0.0;
     }
     __syncthreads();
 
@@ -1474,10 +1489,10 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
 // eight waves per SIMD (four workgroups per CU, as the LDS allows): the
 // register bound this sets makes the high and full products' K4 about 12%
 // faster at n = 2^30
-template <int KIND, bool DIAG, int B>
+template <int KIND, bool DIAG, int B, typename C = double2>
 __global__ __launch_bounds__(NT4, K4_WAVES) void k4_backmap_carry(KParams p)
 {
-    k4_body<KIND, DIAG, B>(p, blk_hw());
+    k4_body<KIND, DIAG, B, C>(p, blk_hw());
 }
 
 template <int KIND, int B>

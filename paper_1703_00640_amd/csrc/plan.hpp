@@ -34,6 +34,7 @@ constexpr uint32_t L2_MAX = 1024, L1_MAX = 4096, LM_MAX = 256;
 constexpr int DPW_HOST = TM_DPT * TM_NT4;  // coefficients per K4 workgroup
 
 struct Plan {
+    bool df = false;    // FP32 path: double-float FFT passes
     int req_kind = 0;   // requested tm_kind
     int kind = 0;       // algorithm run (TM_FULL/TM_LO/TM_HI)
     bool via_full = false;
@@ -144,6 +145,13 @@ inline bool split_M3(uint64_t M, uint32_t force, uint32_t& L1, uint32_t& Lm, uin
 }
 
 // smallest N in {2^a, 3*2^a, 5*2^(a>=5), 7*2^(a>=5)}, N >= max(x, 64)
+inline uint64_t next_pow2(uint64_t x)
+{
+    uint64_t p = 64;
+    while (p < x) p *= 2;
+    return p;
+}
+
 inline uint64_t next_smooth(uint64_t x)
 {
     if (x < 64) x = 64;
@@ -161,19 +169,32 @@ inline uint64_t next_smooth(uint64_t x)
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Digit sizes of the FP32 path (double-float FFT passes, about 48 bits
+// against FP64's 53, measured 2^-47 relative error per transform): the
+// rounding error grows as the unit roundoff times 2^(3b) for the truncated
+// products and 2^(2b) for the full product (the bounds on the convolution's
+// coefficients, Sections 2.3 and 3.4), so keeping the FP64 plans' margin
+// costs ceil(6/3) = 2 bits of b (11 -> 9) and ceil(6/2) = 3 bits (16 -> 13).
+constexpr int B_TRUNC_DF = 9;
+constexpr int B_FULL_DF = 13;
+
 // Build the plan.  b_trunc / b_full: digit sizes (0 = default).  via_full:
 // serve a low or high product by the full product plus extraction at any n
-// (the checked entry point's last fallback).  Returns false if unsupported.
+// (the checked entry point's last fallback).  df: the FP32 path (power-of-two
+// lengths, double-float FFT passes).  Returns false if unsupported.
 inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P, uint32_t force = 0,
-                      bool via_full = false)
+                      bool via_full = false, bool df = false)
 {
     if (n == 0 || kind < 0 || kind > 2) return false;
     P = Plan();
     P.req_kind = kind;
     P.n = n;
     P.L = (n + 63) / 64;
-    const int bt = b_trunc ? b_trunc : B_TRUNC;
-    const int bf = b_full ? b_full : B_FULL;
+    P.df = df;
+    const int bt = b_trunc ? b_trunc : df ? B_TRUNC_DF : B_TRUNC;
+    const int bf = b_full ? b_full : df ? B_FULL_DF : B_FULL;
+    uint64_t (*next_len)(uint64_t) = df ? next_pow2 : next_smooth;
+    if (df && (force & SPLIT_ODD_ROW)) return false;
     if (bt < B_MIN || bt > B_MAX || bf < B_MIN || bf > B_MAX) return false;
     P.via_full = kind != TM_FULL && (n < TRUNC_MIN_BITS || via_full);
     P.kind = P.via_full ? TM_FULL : kind;
@@ -182,7 +203,7 @@ inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P, ui
         P.b = bf;
         P.lam = 0;
         uint64_t nd = (n + P.b - 1) / P.b;
-        P.N = next_smooth(2 * nd);
+        P.N = next_len(2 * nd);
         P.digits = P.N / 2;
         P.ncoef = P.N;
         if (kind == TM_FULL) { P.off = 0; P.out_bits = 128 * P.L; P.out_limbs = 2 * P.L; }
@@ -192,12 +213,12 @@ inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P, ui
         P.b = bt;
         const int b = P.b;
         if (kind == TM_LO) {
-            P.N = next_smooth((n + b - 1) / b);
+            P.N = next_len((n + b - 1) / b);
             P.digits = P.N;
             P.ncoef = P.N;
         } else {
-            uint64_t N = next_smooth((n + b - 1) / b);
-            while ((N + 1) * (uint64_t)b < n + (uint64_t)lg_ceil(N) + 2) N = next_smooth(N + 1);
+            uint64_t N = next_len((n + b - 1) / b);
+            while ((N + 1) * (uint64_t)b < n + (uint64_t)lg_ceil(N) + 2) N = next_len(N + 1);
             P.N = N;
             P.digits = N + 1;
             P.ncoef = N + 1;
@@ -254,9 +275,11 @@ inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P, ui
 //     inter-pass twiddles and the 1/M scaling, and t = 2^-49;
 //   * the truncated products scale by 2^b and the back map's gain g, and the
 //     series truncation adds at most 2^-8 (the choice of lambda).
-inline double conv_eta(uint64_t M)
+inline double conv_eta(uint64_t M, bool df = false)
 {
-    const double u = ldexp(1.0, -53), t = ldexp(1.0, -49);
+    // double-float: unit roundoff 2^-47 per operation (measured relative
+    // error of a whole transform), twiddles split from FP64 (2^-47 too)
+    const double u = ldexp(1.0, df ? -47 : -53), t = ldexp(1.0, df ? -47 : -49);
     const double k = (double)(lg_ceil(M) + 4);
     return expm1(3 * k * log1p(u) + (3 * k + 1) * log1p(sqrt(5.0) * u) + 3 * k * log1p(t));
 }
@@ -264,7 +287,7 @@ inline double conv_eta(uint64_t M)
 // Bound on |x - exact| over all rounded values x of plan P (see above).
 inline double rounding_bound(const Plan& P)
 {
-    const double eta = conv_eta(P.M);
+    const double eta = conv_eta(P.M, P.df);
     if (P.kind == TM_FULL) {
         const double nrm2 = (double)(P.digits - 1) * ldexp(1.0, 2 * P.b - 2) + ldexp(1.0, 2 * P.b);
         return nrm2 * eta;

@@ -534,6 +534,36 @@ tm_status plan_for(tm_kind kind, uint64_t n, Plan& P, int bt = 0, int bf = 0)
     return TM_OK;
 }
 
+// Plan of the FP32 path: the planner with double-float digit sizes and
+// power-of-two lengths; forced digit sizes and splits from the same
+// environment variables as the FP64 plans (odd-row splits do not apply).
+tm_status plan_fp32c(tm_kind kind, uint64_t n, Plan& P)
+{
+    if (kind != TM_FULL && kind != TM_LO && kind != TM_HI) {
+        g_last_error = "invalid kind";
+        return TM_ERR_INVALID;
+    }
+    if (n == 0) {
+        g_last_error = "n_bits must be positive";
+        return TM_ERR_INVALID;
+    }
+    int bt = 0, bf = 0;
+    const char* e = getenv("TM_FORCE_B");
+    if (e && *e) bt = atoi(e);
+    e = getenv("TM_FORCE_B_FULL");
+    if (e && *e) bf = atoi(e);
+    uint32_t flm = 0;
+    e = getenv("TM_FORCE_LM");
+    if (e && *e) flm = (uint32_t)atoi(e);
+    e = getenv("TM_FORCE_LG2");
+    if (e && *e) flm = split_code(flm, atoi(e));
+    if (!make_plan((int)kind, n, bt, bf, P, flm, false, true)) {
+        g_last_error = "unsupported size";
+        return TM_ERR_UNSUPPORTED;
+    }
+    return TM_OK;
+}
+
 enum Mode { RUN, DIAG_RUN };
 
 tm_status run(const Plan& P, uint64_t* w, const uint64_t* u, const uint64_t* v, void* ws,
@@ -565,39 +595,46 @@ tm_status run(const Plan& P, uint64_t* w, const uint64_t* u, const uint64_t* v, 
         p.dbg_c = dc;
         p.dbg_x = dx;
     }
+    // FP64 path, or the FP32 path's double-float instances (P.df)
     int ne = 0;
     if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
-    if (!launch_k1_any(P.kind, p, s)) {
+    if (!(P.df ? launch_k1_fp32c(P.kind, P.L1, p, s) : launch_k1_any(P.kind, p, s))) {
         g_last_error = "no kernel for L1";
         return TM_ERR_UNSUPPORTED;
     }
     if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
     if (P.Lm > 1) {
-        if (!launch_mid<false>(p, s)) {
+        if (!(P.df ? launch_mid_fp32c<false>(p, s) : launch_mid<false>(p, s))) {
             g_last_error = "no kernel for Lm";
             return TM_ERR_UNSUPPORTED;
         }
         if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
     }
-    if (!launch_k2(P.L2, p, s)) {
+    if (!(P.df ? launch_k2_fp32c(P.L2, p, s) : launch_k2(P.L2, p, s))) {
         g_last_error = "no kernel for L2";
         return TM_ERR_UNSUPPORTED;
     }
     if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
     if (P.Lm > 1) {
-        if (!launch_mid<true>(p, s)) {
+        if (!(P.df ? launch_mid_fp32c<true>(p, s) : launch_mid<true>(p, s))) {
             g_last_error = "no kernel for Lm";
             return TM_ERR_UNSUPPORTED;
         }
         if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
     }
-    if (!launch_k3(P.L1, p, s)) {
+    if (!(P.df ? launch_k3_fp32c(P.L1, p, s) : launch_k3(P.L1, p, s))) {
         g_last_error = "no kernel for L1";
         return TM_ERR_UNSUPPORTED;
     }
     if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
-    if (mode == DIAG_RUN) launch_k4<true>(P.kind, p, s);
-    else launch_k4<false>(P.kind, p, s);
+    if (P.df) {
+        if (mode == DIAG_RUN) launch_k4_fp32c<true>(P.kind, p, s);
+        else launch_k4_fp32c<false>(P.kind, p, s);
+    } else if (mode == DIAG_RUN) {
+        launch_k4<true>(P.kind, p, s);
+    } else {
+        launch_k4<false>(P.kind, p, s);
+    }
     if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
     HIP_TRY(hipGetLastError());
     return TM_OK;
@@ -967,6 +1004,52 @@ tm_status tm_mul(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v
     if (st != TM_OK) return st;
     return run(P, w, u, v, workspace, workspace_bytes, stream, guard_dev, RUN, nullptr, nullptr,
                nullptr);
+}
+
+size_t tm_workspace_bytes_fp32c(tm_kind kind, uint64_t n_bits)
+{
+    Plan P;
+    return plan_fp32c(kind, n_bits, P) == TM_OK ? P.ws_bytes : 0;
+}
+
+tm_status tm_plan_query_fp32c(tm_kind kind, uint64_t n_bits, tm_plan_info* out)
+{
+    if (!out) {
+        g_last_error = "null pointer";
+        return TM_ERR_INVALID;
+    }
+    Plan P;
+    tm_status st = plan_fp32c(kind, n_bits, P);
+    if (st != TM_OK) return st;
+    fill_info(kind, n_bits, P, out);
+    return TM_OK;
+}
+
+tm_status tm_mul_fp32c(tm_kind kind, uint64_t* w, const uint64_t* u, const uint64_t* v,
+                       uint64_t n_bits, void* workspace, size_t workspace_bytes, hipStream_t stream,
+                       tm_guard* guard_dev)
+{
+    Plan P;
+    tm_status st = plan_fp32c(kind, n_bits, P);
+    if (st != TM_OK) return st;
+    return run(P, w, u, v, workspace, workspace_bytes, stream, guard_dev, RUN, nullptr, nullptr,
+               nullptr);
+}
+
+tm_status tm_coefficients_fp32c(tm_kind kind, int64_t* coeffs, double* x, uint64_t coeffs_len,
+                                const uint64_t* u, const uint64_t* v, uint64_t n_bits,
+                                void* workspace, size_t workspace_bytes, hipStream_t stream,
+                                tm_guard* guard_dev)
+{
+    Plan P;
+    tm_status st = plan_fp32c(kind, n_bits, P);
+    if (st != TM_OK) return st;
+    if (coeffs_len < P.ncoef) {
+        g_last_error = "coefficient buffer too small";
+        return TM_ERR_INVALID;
+    }
+    return run(P, nullptr, u, v, workspace, workspace_bytes, stream, guard_dev, DIAG_RUN, coeffs,
+               x, nullptr);
 }
 
 size_t tm_noalloc_max_bytes(void) { return NOALLOC_MAX; }

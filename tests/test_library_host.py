@@ -259,3 +259,21 @@ def test_odd_factor_in_rows_split(monkeypatch):
     assert (p["L1"], p["Lm"], p["L2"]) == (64, 1, 768)
     with pytest.raises(tm.TmulError):
         tm.plan("lo", 3000000)  # N = 5 2^16
+
+
+def test_fp32c_plans():
+    """Digit sizes 9 (truncated) and 13 (full), power-of-two lengths, the
+    theorems' size constraints (Nb >= n low, (N+1)b >= n + lg N + 2 high)."""
+    import paper_1703_00640_amd as tm
+    for n in (5000, 1 << 16, 100003, 1 << 22, 1 << 26, 1 << 30):
+        for kind in ("lo", "hi", "full"):
+            p = tm.plan(kind, n, fp32c=True)
+            if p["via_full"]:
+                continue
+            N, b = p["N"], p["b"]
+            assert N & (N - 1) == 0 and p["L1"] * p["Lm"] * p["L2"] == p["M"]
+            assert b == (13 if kind == "full" else 9)
+            if kind == "lo":
+                assert N * b >= n
+            elif kind == "hi":
+                assert (N + 1) * b >= n + (N - 1).bit_length() + 2
