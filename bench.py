@@ -50,7 +50,8 @@ def kernel_bytes(plan, n_bits, kind):
     N = plan["N"]
     L = (n_bits + 63) // 64
     out = 16 * L if kind == "full" else 8 * L
-    return {"split_map_colfft": 2 * 8 * L + 16 * N,
+    return {"fused_fft": 2 * 8 * L + 8 * N,
+            "split_map_colfft": 2 * 8 * L + 16 * N,
             "mid_colfft": 32 * N,
             "rowfft_pointwise_rowifft": 24 * N,
             "mid_colifft": 16 * N,
@@ -89,10 +90,13 @@ def stored_traffic(log2n):
     return out if src == source_hash() else {}
 
 
-def pmc_pass(n_bits):
-    """Workload for rocprofv3 counter passes: each product twice (after the
-    autotuner's timing runs), then a plain 256 MiB device copy (the
-    calibration kernel for FETCH_SIZE and WRITE_SIZE)."""
+def pmc_pass(n_bits, reps=2):
+    """Workload for rocprofv3 runs (kernel trace and counter passes): the
+    autotuner's timing runs for every kind (the benchmark's FFT splits),
+    then a marker dispatch (a fill of a 16-bit integer tensor, the only one
+    in the run), then `reps` products of each kind, then a plain 256 MiB
+    device copy (the calibration kernel for FETCH_SIZE and WRITE_SIZE).
+    Summaries take the dispatches between the marker and the copy."""
     import torch
     import paper_1703_00640_amd as tm
     from paper_1703_00640_amd import inputs
@@ -100,11 +104,16 @@ def pmc_pass(n_bits):
     u, v = inputs.operand_pair(n_bits, 5)
     du = torch.from_numpy(u.view(np.int64)).to(dev)
     dv = torch.from_numpy(v.view(np.int64)).to(dev)
-    for k in ("lo", "hi", "full"):
+    kinds = ("lo", "hi", "full")
+    for k in kinds:
         tm.autotune(k, n_bits)  # the same FFT split as the benchmark
-        ws = torch.empty(tm.plan(k, n_bits)["workspace_bytes"], dtype=torch.uint8, device=dev)
-        for _ in range(2):
-            tm.mul(k, du, dv, n_bits, workspace=ws)
+    ws = {k: torch.empty(tm.plan(k, n_bits)["workspace_bytes"], dtype=torch.uint8, device=dev)
+          for k in kinds}
+    torch.cuda.synchronize()
+    torch.full((1,), 3, dtype=torch.int16, device=dev)  # marker
+    for k in kinds:
+        for _ in range(reps):
+            tm.mul(k, du, dv, n_bits, workspace=ws[k])
     a = torch.ones(1 << 25, dtype=torch.float64, device=dev)
     b = torch.empty_like(a)
     for _ in range(2):
@@ -165,6 +174,22 @@ def serving_bench(count=4096, n_streams=4):
         st, _, _ = serving.run(m, arr, n_streams=n_streams)
         st["offered_rps"] = rate
         out["poisson_%.1f" % frac] = st
+    # the same server with batches captured into HIP graphs: every batch of
+    # two or more requests, and only batches of 16 or more
+    for mode, key in ((True, "graph_mode"), ("auto", "graph_mode_auto")):
+        gsat, _, _ = serving.run(m, np.zeros(count), n_streams=n_streams, graphs=mode)
+        rate = 0.5 * sat["throughput_rps"]
+        gp, _, _ = serving.run(m, inputs.poisson_arrivals(count, rate, seed=8), n_streams=n_streams,
+                               graphs=mode)
+        gq, _, _ = serving.run(m, inputs.poisson_arrivals(count, 1.8 * rate, seed=8),
+                               n_streams=n_streams, graphs=mode)
+        out[key] = {"saturated_throughput_rps": gsat["throughput_rps"],
+                    "poisson_0.5": {"p50_ms": gp["p50_ms"], "p99_ms": gp["p99_ms"],
+                                    "throughput_rps": gp["throughput_rps"]},
+                    "poisson_0.9": {"p50_ms": gq["p50_ms"], "p99_ms": gq["p99_ms"],
+                                    "throughput_rps": gq["throughput_rps"]},
+                    "guard_flags": gsat["guard_flags"] | gp["guard_flags"] | gq["guard_flags"],
+                    "failed": gsat["failed"] + gp["failed"] + gq["failed"]}
     # storage: the truncated products' transforms hold N = 3n/b' reals
     # against 2N for the full product; admission capacity of a 1 GiB pool
     cap = {}
@@ -496,7 +521,7 @@ def main():
                     help="run the counter-collection workload instead of the benchmark")
     args = ap.parse_args()
     if args.pmc_pass:
-        pmc_pass(1 << args.log2n)
+        pmc_pass(1 << args.log2n, args.steps)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

@@ -106,6 +106,9 @@ typedef struct {
     uint32_t guaranteed;    /* 1 if rounding_bound <= 0.45 (see tm_mul_guaranteed) */
     double rounding_bound;  /* worst-case bound on |x - exact| over the rounded
                                values x of this plan (tm_mul_guaranteed)         */
+    uint32_t fused;         /* 1 if one workgroup per product runs the whole
+                               transform in LDS (M <= 4096; two launches)        */
+    uint32_t reserved;
 } tm_plan_info;
 
 /* One request of a batch: w = product(kind, u, v) on n_bits-bit operands. */
@@ -209,6 +212,19 @@ size_t tm_batch_meta_bytes(size_t count);
 tm_status tm_mul_packed(const tm_request* reqs, size_t count, void* const* workspaces,
                         const size_t* workspace_bytes, void* meta, size_t meta_bytes,
                         hipStream_t stream, tm_guard* const* guards_dev);
+
+/*
+ * tm_mul_packed with a caller-owned host staging buffer for the launch
+ * metadata (host_staging: pinned host memory of host_staging_bytes >=
+ * tm_batch_meta_bytes(count) bytes, which the caller keeps untouched until
+ * the batch has run).  The library then holds no buffer of its own across
+ * the call, so the whole call may be captured into a HIP graph (stream
+ * capture) once every size's tables exist (tm_prepare).
+ */
+tm_status tm_mul_packed_staged(const tm_request* reqs, size_t count, void* const* workspaces,
+                               const size_t* workspace_bytes, void* meta, size_t meta_bytes,
+                               void* host_staging, size_t host_staging_bytes, hipStream_t stream,
+                               tm_guard* const* guards_dev);
 
 /*
  * Like tm_mul, then synchronises the stream and reads the guard.  If it
@@ -401,6 +417,25 @@ void tm_server_destroy(tm_server* s);          /* waits for running requests */
 tm_status tm_serve_trace(const tm_request* reqs, const double* arrival_s, size_t count,
                          size_t pool_bytes, int n_streams, int max_inflight, double* latency_s,
                          tm_guard* guards_host, double* makespan_s);
+
+/*
+ * Graph mode: a batch is captured (stream capture of its copies, packed
+ * multiplication with a server-owned metadata staging buffer, and result
+ * copies) into a HIP graph that is instantiated and launched as one unit; a
+ * batch whose capture fails (pageable host buffers) is launched directly.
+ * Results are the same either way.  mode 0: never (default); 1: every batch
+ * of two or more requests; 2: batches of 16 or more requests (one graph
+ * launch then outweighs the capture and instantiation of a graph used once).
+ */
+tm_status tm_server_use_graphs(tm_server* s, int mode);
+
+/* tm_serve_trace with flags: TM_SERVE_GRAPHS runs the server in graph mode
+ * 1, TM_SERVE_GRAPHS_AUTO in graph mode 2. */
+#define TM_SERVE_GRAPHS 1
+#define TM_SERVE_GRAPHS_AUTO 2
+tm_status tm_serve_trace_ex(const tm_request* reqs, const double* arrival_s, size_t count,
+                            size_t pool_bytes, int n_streams, int max_inflight, double* latency_s,
+                            tm_guard* guards_host, double* makespan_s, int flags);
 
 const char* tm_status_string(tm_status s);
 const char* tm_last_error(void);

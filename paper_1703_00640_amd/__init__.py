@@ -47,7 +47,8 @@ class _PlanInfo(ctypes.Structure):
                 ("digits", ctypes.c_uint64), ("M", ctypes.c_uint64),
                 ("L1", ctypes.c_uint32), ("L2", ctypes.c_uint32),
                 ("workspace_bytes", ctypes.c_uint64), ("Lm", ctypes.c_uint32),
-                ("guaranteed", ctypes.c_uint32), ("rounding_bound", ctypes.c_double)]
+                ("guaranteed", ctypes.c_uint32), ("rounding_bound", ctypes.c_double),
+                ("fused", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class _Request(ctypes.Structure):
@@ -134,6 +135,10 @@ def _load():
                                    SZ, I32, I32, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(Guard), ctypes.POINTER(ctypes.c_double)]
     lib.tm_serve_trace.restype = I32
+    lib.tm_serve_trace_ex.argtypes = lib.tm_serve_trace.argtypes + [I32]
+    lib.tm_serve_trace_ex.restype = I32
+    lib.tm_server_use_graphs.argtypes = [P, I32]
+    lib.tm_server_use_graphs.restype = I32
     lib.tm_status_string.argtypes = [I32]
     lib.tm_status_string.restype = ctypes.c_char_p
     lib.tm_last_error.argtypes = []
@@ -431,13 +436,15 @@ class Server:
     host tensors are admitted by device memory and overlap on the device.
     Keep every submitted tensor alive until its request is polled."""
 
-    def __init__(self, pool_bytes=1 << 30, n_streams=4, max_inflight=0):
+    def __init__(self, pool_bytes=1 << 30, n_streams=4, max_inflight=0, graphs=False):
         lib = _load()
         h = ctypes.c_void_p()
         _check(lib.tm_server_create(int(pool_bytes), int(n_streams), int(max_inflight),
                                     ctypes.byref(h)), "server create")
         self._h = h
         self._keep = {}
+        if graphs:
+            _check(lib.tm_server_use_graphs(h, 2 if graphs == "auto" else 1), "server graphs")
 
     def submit(self, kind, u, v, n_bits, out):
         k, L = _kind(kind), nlimbs(n_bits)
@@ -479,9 +486,12 @@ class Server:
             pass
 
 
-def serve_trace(requests, arrival_s, pool_bytes=1 << 30, n_streams=4, max_inflight=0):
+def serve_trace(requests, arrival_s, pool_bytes=1 << 30, n_streams=4, max_inflight=0,
+                graphs=False):
     """Replay an arrival trace (tm_serve_trace).  requests: list of
     (kind, u, v, n_bits, out) with CPU tensors (pinned for overlap).
+    graphs: True runs every batch as a captured HIP graph (TM_SERVE_GRAPHS),
+    "auto" only batches of 16 or more (TM_SERVE_GRAPHS_AUTO).
     Returns (latency_s list, guards list, makespan_s)."""
     lib = _load()
     cnt = len(requests)
@@ -494,6 +504,7 @@ def serve_trace(requests, arrival_s, pool_bytes=1 << 30, n_streams=4, max_inflig
     lat = (ctypes.c_double * cnt)()
     guards = (Guard * cnt)()
     mk = ctypes.c_double()
-    _check(lib.tm_serve_trace(reqs, arr, cnt, int(pool_bytes), int(n_streams), int(max_inflight),
-                              lat, guards, ctypes.byref(mk)), "serve_trace")
+    _check(lib.tm_serve_trace_ex(reqs, arr, cnt, int(pool_bytes), int(n_streams), int(max_inflight),
+                                 lat, guards, ctypes.byref(mk),
+                                 2 if graphs == "auto" else 1 if graphs else 0), "serve_trace")
     return list(lat), [guards[i] for i in range(cnt)], mk.value

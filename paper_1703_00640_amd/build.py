@@ -7,8 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtmul.so")
 SOURCES = [os.path.join(HERE, "csrc", f)
-           for f in ("tmul.hip", "k1_full.hip", "k1_lo.hip", "k1_hi.hip", "fp32c.hip", "serve.cpp",
-                     "mulmod.hip")]
+           for f in ("tmul.hip", "k1_full.hip", "k1_lo.hip", "k1_hi.hip", "k0_small.hip", "fp32c.hip",
+                     "serve.cpp", "mulmod.hip")]
 DEPS = SOURCES + [os.path.join(HERE, "csrc", f)
                   for f in ("kernels.hpp", "fft_tile.hpp", "dfloat.hpp", "plan.hpp", "dispatch.hpp")] \
     + [os.path.join(ROOT, "include", "tmul.h")]

@@ -24,7 +24,13 @@ constexpr int w_for(int L1, int tile, int wmax)
     while (w * 2 <= lim) w *= 2;
     return w;
 }
-constexpr int w1_for(int kind, int L1, bool wide) { return w_for(L1, TILE1, kind == K_FULL && wide ? 16 : 8); }
+#ifndef TM_K1_TRUNC_WIDE
+#define TM_K1_TRUNC_WIDE 0
+#endif
+constexpr int w1_for(int kind, int L1, bool wide)
+{
+    return w_for(L1, TILE1, (kind == K_FULL || TM_K1_TRUNC_WIDE) && wide ? 16 : 8);
+}
 constexpr int w3_for(int L1, bool wide) { return w_for(L1, TILE3, wide ? 16 : 8); }
 inline bool wide_tiles(const KParams& p) { return p.Lm > 1; }
 
@@ -99,6 +105,10 @@ bool launch_k1_hi(uint32_t L1, const KParams& p, hipStream_t s);
 bool launch_k1g_full(uint32_t L1, int fb, bool wide, const Group& g, uint32_t blocks, hipStream_t s);
 bool launch_k1g_lo(uint32_t L1, int fb, bool wide, const Group& g, uint32_t blocks, hipStream_t s);
 bool launch_k1g_hi(uint32_t L1, int fb, bool wide, const Group& g, uint32_t blocks, hipStream_t s);
+
+// fused small-size pass, defined in k0_small.hip
+bool launch_k0(int kind, uint32_t L1, uint32_t L2, const KParams& p, hipStream_t s);
+bool launch_k0g(int kind, uint32_t L1, uint32_t L2, const Group& g, uint32_t blocks, hipStream_t s);
 
 // FP32 path (double-float FFT passes), defined in fp32c.hip
 bool launch_k1_fp32c(int kind, uint32_t L1, const KParams& p, hipStream_t s);

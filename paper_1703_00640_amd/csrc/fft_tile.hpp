@@ -314,6 +314,14 @@ __device__ __forceinline__ C tw_half(const C* twl, int e)
     }
 }
 
+// Stage twiddles: every one read from the LDS table (TM_TW_DIRECT=1, LDS
+// reads for VALU work), or one read per butterfly and the others formed as
+// its powers (0).
+#ifndef TM_TW_DIRECT
+#define TM_TW_DIRECT 0
+#endif
+constexpr bool TW_DIRECT = TM_TW_DIRECT != 0;
+
 // One Stockham stage of radix R after NS points have been combined.
 template <int P, int R, int NS, int NB, int NT, bool INV, bool COLS, int RS, int PS, typename C>
 __device__ __forceinline__ void fft_stage(C* buf, const C* twl)
@@ -343,12 +351,21 @@ __device__ __forceinline__ void fft_stage(C* buf, const C* twl)
             const int j = jj[q];
             const int k = (NS == 1) ? 0 : j % NS;
             if (NS > 1 && k != 0) {
-                // one table read per butterfly, the other twiddles as powers
-                const C w1 = tw_half<P>(twl, k * ESTEP);
-                C pw[R];
-                tw_powers<R>(INV ? cconj(w1) : w1, pw);
+                if constexpr (TW_DIRECT) {
+                    // every twiddle read from the LDS table (r k ESTEP < P)
 #pragma unroll
-                for (int r = 1; r < R; r++) v[q][r] = cmul(v[q][r], pw[r]);
+                    for (int r = 1; r < R; r++) {
+                        const C w = tw_half<P>(twl, r * k * (int)ESTEP);
+                        v[q][r] = cmul(v[q][r], INV ? cconj(w) : w);
+                    }
+                } else {
+                    // one table read per butterfly, the other twiddles as powers
+                    const C w1 = tw_half<P>(twl, k * ESTEP);
+                    C pw[R];
+                    tw_powers<R>(INV ? cconj(w1) : w1, pw);
+#pragma unroll
+                    for (int r = 1; r < R; r++) v[q][r] = cmul(v[q][r], pw[r]);
+                }
             }
             dftR<R, INV>(v[q]);
             const int out = (j - k) * R + k;

@@ -105,7 +105,7 @@ struct KParams {
     uint32_t ncoef;     // rounded coefficients (low N, high N+1, full N)
     uint32_t ncover;    // digit positions carried (multiple of DPW)
     uint32_t nstatus;   // K4 workgroups
-    uint32_t pad0;
+    uint32_t fused;     // 1: K0 replaces K1, K2, K3 (small sizes)
     double invN, invM;
     double cf[LMAX];        // c_r of the forward map: alpha (-eps)^r/r!, gamma eps^r/r!
     double cb[LMAX];        // c_r of the back map: beta eps^r/r!, delta (-eps)^r/r!
@@ -963,6 +963,165 @@ __global__ __launch_bounds__(NT3) void k3_col_inverse_g(Group g)
     const Blk bk = group_block(g, pi);
     const KParams& p = group_params(g, pi);
     k3_body<L1, W>(p, bk);
+}
+
+// ------------------------------------------------------------------- K0
+
+// Fused small-size pass: one workgroup computes both operands' digits and
+// maps, their whole length-M transforms (M = L1 L2 <= 4096: both packed
+// spectra fit in LDS), the pointwise product and the whole inverse
+// transform, and writes the real convolution for K4 (which then rounds and
+// carries).  It replaces K1, K2 and K3 of the four-step path, so a small
+// product is two launches, and a packed batch of small products is one K0
+// launch (one workgroup per product) plus one K4 launch.
+constexpr int NT0 = 256;
+constexpr uint32_t K0_MAX_M = 4096;
+
+template <int L1, int L2, int KIND>
+__device__ __forceinline__ void k0_body(const KParams& p)
+{
+    constexpr int M = L1 * L2;
+    static_assert(M <= (int)K0_MAX_M, "fused pass holds both spectra in LDS");
+    constexpr int LB = k1_lb(KIND, 0), LO = LB - 1;
+    constexpr int WC = 8;                   // complex points per digit row
+    static_assert(L2 % WC == 0, "row chunks");
+    constexpr int ND = k1_nd(WC, KIND, 0);
+    constexpr int CH = L2 / WC;
+    constexpr int UNITS = 2 * L1 * CH;      // (operand, row, chunk)
+    __shared__ double2 A[padded(M)], B[padded(M)];
+    __shared__ double2 tw1[twl_size(L1)], tw2[twl_size(L2)];
+    __shared__ double s_th[2][LMAX + 8];
+    const int tid = threadIdx.x;
+    const bool square = p.zb == p.za;
+
+    clear_state(p, tid, NT0);
+    load_twl<L1, NT0>(tw1, p.tw1);
+    load_twl<L2, NT0>(tw2, p.tw2);
+    if (KIND == K_HI && tid <= (int)p.jmax && tid <= (int)p.N) {
+        s_th[0][tid] = ldexp((double)bal_digit(p, p.u, (int64_t)p.N - tid, p.digits, true), -tid * p.b);
+        s_th[1][tid] = ldexp((double)bal_digit(p, p.v, (int64_t)p.N - tid, p.digits, true), -tid * p.b);
+    }
+    // G = alpha* U / gamma-dagger F (truncated products) or the digits (full
+    // product) of both operands, element (j1, col) at index j1 L2 + col.
+    // The loop is unrolled so that every unit's limb loads are in flight
+    // together.
+    const int64_t kf_min = KIND == K_HI ? (int64_t)p.jmax : 0;
+    const int64_t top = (int64_t)p.digits - 1;
+    constexpr int PU = (UNITS + NT0 - 1) / NT0;
+#pragma unroll
+    for (int qu = 0; qu < PU; qu++) {
+        const int ux = tid + qu * NT0;
+        if (UNITS % NT0 != 0 && ux >= UNITS) continue;
+        const int op = ux / (L1 * CH);
+        const int rem = ux % (L1 * CH);
+        const uint32_t m0 = (uint32_t)(rem / CH) * L2 + (uint32_t)(rem % CH) * WC;
+        const uint64_t* x = op ? p.v : p.u;
+        const int64_t kf = 2 * (int64_t)m0 - LO;
+        const bool fast = kf >= kf_min && (KIND != K_FULL || kf + ND <= top);
+        int32_t d[ND];
+        double2 g[WC];
+        if (fast) row_digits_reg<ND>(p, x, kf, d);
+        else row_digits_edge<ND, KIND>(p, x, kf, d);
+        if constexpr (KIND == K_FULL) {
+#pragma unroll
+            for (int c = 0; c < WC; c++) g[c] = make_double2((double)d[2 * c], (double)d[2 * c + 1]);
+        } else if (fast) {
+            row_map_fast<WC, ND, LB>(p, kf, d, g);
+        } else {
+            const double FN = KIND == K_HI ? (double)bal_digit(p, x, p.N, p.digits, true) : 0.0;
+            row_map_edge<WC, KIND, ND, LB>(p, m0, FN, d, g);
+        }
+        double2* dst = op ? B : A;
+#pragma unroll
+        for (int c = 0; c < WC; c++) dst[pidx(m0 + c)] = g[c];
+    }
+    __syncthreads();
+    if (KIND == K_HI && tid == 0) {
+        // theta = rho^-N F(rho), rho ~ 2^b: sum_j 2^(-jb) F_(N-j), j <= jmax
+        double t0 = 0.0, t1 = 0.0;
+        for (int j = 0; j <= (int)p.jmax && j <= (int)p.N; j++) {
+            t0 += s_th[0][j];
+            t1 += s_th[1][j];
+        }
+        p.theta[0] = t0;
+        p.theta[1] = square ? t0 : t1;
+    }
+    // forward: L1-point column DFTs, twiddles exp(-2 pi i col k1 / M),
+    // L2-point row DFTs; position (k1, k2) then holds bin k1 + L1 k2
+    // Twiddles of this thread's elements e = tid + q NT0: L2 divides NT0, so
+    // col = e mod L2 is fixed and k1 = e / L2 steps by NT0 / L2; the
+    // exponents col k1 (inter-pass) and k1 + L1 col (pointwise bin) are
+    // arithmetic progressions in q, formed from two table values each.
+    static_assert(NT0 % L2 == 0, "row length divides the workgroup");
+    constexpr int PE = (M + NT0 - 1) / NT0;
+    const uint32_t col = (uint32_t)(tid % L2), r1 = (uint32_t)(tid / L2), dk = (uint32_t)(NT0 / L2);
+    TwSeq<PE> tip, tbin;
+    tip.init(tw_get<false>(p.tw, (col * r1) % M), tw_get<false>(p.tw, (col * dk) % M));
+    tbin.init(tw_get<false>(p.tw, (r1 + L1 * col) % M), tw_get<false>(p.tw, dk % M));
+    tile_fft<L1, L2, NT0, false, true>(A, tw1);
+    tile_fft<L1, L2, NT0, false, true>(B, tw1);
+#pragma unroll
+    for (int q = 0; q < PE; q++) {
+        const int e = tid + q * NT0;
+        if (M % NT0 == 0 || e < M) {
+            const double2 w = tip.at(q);
+            A[pidx(e)] = cmul(A[pidx(e)], w);
+            B[pidx(e)] = cmul(B[pidx(e)], w);
+        }
+    }
+    __syncthreads();
+    tile_fft<L2, L1, NT0, false, false, L2>(A, tw2);
+    tile_fft<L2, L1, NT0, false, false, L2>(B, tw2);
+    // pointwise product over mirror pairs (bin k, bin M - k), each pair
+    // read and written by one thread
+#pragma unroll
+    for (int q = 0; q < PE; q++) {
+        const int e = tid + q * NT0;
+        if (M % NT0 != 0 && e >= M) continue;
+        const int k1 = e / L2, k2 = e % L2;
+        const int mk1 = k1 ? L1 - k1 : 0, mk2 = k1 ? L2 - 1 - k2 : (L2 - k2) % L2;
+        const int em = mk1 * L2 + mk2;
+        if (e > em) continue;
+        // exp(-2 pi i k / M) for bin k = k1 + L1 k2, and its conjugate for M - k
+        const double2 wk = tbin.at(q);
+        const double2 Ya = A[pidx(e)], Yam = A[pidx(em)], Yb = B[pidx(e)], Ybm = B[pidx(em)];
+        const double2 qe = pointwise_bin(Ya, Yam, Yb, Ybm, wk);
+        if (em != e) {
+            const double2 qm = pointwise_bin(Yam, Ya, Ybm, Yb, cconj(wk));
+            A[pidx(em)] = qm;
+        }
+        A[pidx(e)] = qe;
+    }
+    __syncthreads();
+    // inverse: row DFTs, twiddles exp(+2 pi i j2 k1 / M), column DFTs;
+    // position (j1, j2) then holds point j1 L2 + j2 of the product
+    tile_fft<L2, L1, NT0, true, false, L2>(A, tw2);
+#pragma unroll
+    for (int q = 0; q < PE; q++) {
+        const int e = tid + q * NT0;
+        if (M % NT0 == 0 || e < M) A[pidx(e)] = cmul(A[pidx(e)], cconj(tip.at(q)));
+    }
+    __syncthreads();
+    tile_fft<L1, L2, NT0, true, true>(A, tw1);
+#pragma unroll
+    for (int q = 0; q < PE; q++) {
+        const int e = tid + q * NT0;
+        if (M % NT0 == 0 || e < M) p.za[e] = A[pidx(e)];
+    }
+}
+
+template <int L1, int L2, int KIND>
+__global__ __launch_bounds__(NT0) void k0_fused(KParams p)
+{
+    k0_body<L1, L2, KIND>(p);
+}
+
+template <int L1, int L2, int KIND>
+__global__ __launch_bounds__(NT0) void k0_fused_g(Group g)
+{
+    uint32_t pi;
+    (void)group_block(g, pi);
+    k0_body<L1, L2, KIND>(group_params(g, pi));
 }
 
 // ------------------------------------------------------------------- K4

@@ -35,6 +35,7 @@ constexpr int DPW_HOST = TM_DPT * TM_NT4;  // coefficients per K4 workgroup
 
 struct Plan {
     bool df = false;    // FP32 path: double-float FFT passes
+    bool fused = false; // small size: K0 (whole transform in LDS) replaces K1, K2, K3
     int req_kind = 0;   // requested tm_kind
     int kind = 0;       // algorithm run (TM_FULL/TM_LO/TM_HI)
     bool via_full = false;
@@ -178,12 +179,26 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 constexpr int B_TRUNC_DF = 9;
 constexpr int B_FULL_DF = 13;
 
+// (L1, L2) splits with a fused small-size instance (K0): the planner's
+// default split of every length M = N/2 <= 4096 of the menu.
+#define TM_K0_LIST(X)                                                                               \
+    X(2, 16) X(3, 16) X(4, 16) X(5, 16) X(6, 16) X(7, 16) X(8, 16) X(10, 16) X(12, 16) X(14, 16)   \
+    X(16, 16) X(10, 32) X(12, 32) X(14, 32) X(16, 32) X(20, 32) X(24, 32) X(28, 32) X(32, 32)      \
+    X(20, 64) X(24, 64) X(28, 64) X(32, 64) X(40, 64) X(48, 64) X(56, 64) X(64, 64)
+inline bool k0_supported(uint32_t L1, uint32_t L2)
+{
+#define X(A, B) if (L1 == A && L2 == B) return true;
+    TM_K0_LIST(X)
+#undef X
+    return false;
+}
+
 // Build the plan.  b_trunc / b_full: digit sizes (0 = default).  via_full:
 // serve a low or high product by the full product plus extraction at any n
 // (the checked entry point's last fallback).  df: the FP32 path (power-of-two
 // lengths, double-float FFT passes).  Returns false if unsupported.
 inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P, uint32_t force = 0,
-                      bool via_full = false, bool df = false)
+                      bool via_full = false, bool df = false, bool allow_fused = false)
 {
     if (n == 0 || kind < 0 || kind > 2) return false;
     P = Plan();
@@ -238,6 +253,7 @@ inline bool make_plan(int kind, uint64_t n, int b_trunc, int b_full, Plan& P, ui
     }
     P.M = P.N / 2;
     if (!split_M3(P.M, force, P.L1, P.Lm, P.L2)) return false;
+    P.fused = allow_fused && !df && P.Lm == 1 && P.M <= 4096 && k0_supported(P.L1, P.L2);
     uint64_t need = (P.off + P.out_bits + P.b - 1) / P.b + 2;
     uint64_t cov = P.ncoef > need ? P.ncoef : need;
     P.ncover = (cov + DPW_HOST - 1) / DPW_HOST * DPW_HOST;

@@ -126,9 +126,16 @@ struct Batch {
     size_t res_off = 0, res_bytes = 0;  // result region: the jobs' results in order
     hipEvent_t done = nullptr;
     tm_guard* guards_host = nullptr;  // pinned staging of the batch's guards
+    char* meta_host = nullptr;        // pinned staging of its launch metadata (graph mode)
+    hipGraphExec_t graph = nullptr;   // the batch as one captured graph (graph mode)
 };
 
 constexpr size_t kMaxBatch = 64;
+// Smallest batch captured as a graph in the automatic graph mode: one graph
+// launch replaces about one kernel launch per request and stage plus the
+// copies, which pays once the batch is large enough to outweigh the
+// capture and instantiation.
+constexpr size_t kGraphMinBatch = 16;
 
 // Pool block of a batch: launch metadata, then the guards of its requests.
 size_t batch_guard_offset() { return align_up(tm_batch_meta_bytes(kMaxBatch)); }
@@ -144,6 +151,10 @@ struct tm_server {
     std::vector<int> load;                 // requests in flight per stream
     std::vector<hipEvent_t> spare_events;
     std::vector<tm_guard*> spare_guards;   // pinned guard staging buffers
+    std::vector<char*> spare_meta;         // pinned metadata staging buffers (graph mode)
+    int graphs = 0;                        // batches as captured HIP graphs: 0 never,
+                                           // 1 every batch of 2 or more, 2 batches of
+                                           // kGraphMinBatch or more
     std::deque<Job> waiting;
     std::vector<std::deque<Batch>> running;  // per stream, in launch order
     size_t n_running = 0;
@@ -155,9 +166,9 @@ struct tm_server {
 
 namespace {
 
-tm_status launch(tm_server* s, Batch& b)
+// Enqueue a batch's copies, multiplication and guard copy on stream st.
+tm_status enqueue(tm_server* s, Batch& b, hipStream_t st)
 {
-    hipStream_t st = s->streams[b.stream];
     const size_t k = b.jobs.size();
     char* meta = s->base + b.meta_off;
     tm_guard* dg = reinterpret_cast<tm_guard*>(meta + batch_guard_offset());
@@ -186,10 +197,15 @@ tm_status launch(tm_server* s, Batch& b)
         wsb[i] = j.lay.wsb;
         gs[i] = dg + i;
     }
-    tm_status r = k == 1 ? tm_mul((tm_kind)reqs[0].kind, reqs[0].w, reqs[0].u, reqs[0].v, reqs[0].n_bits,
-                                  wss[0], b.jobs[0].lay.wsb, st, gs[0])
-                         : tm_mul_packed(reqs.data(), k, wss.data(), wsb.data(), meta, batch_guard_offset(), st,
-                                         gs.data());
+    tm_status r;
+    if (k == 1)
+        r = tm_mul((tm_kind)reqs[0].kind, reqs[0].w, reqs[0].u, reqs[0].v, reqs[0].n_bits, wss[0],
+                   b.jobs[0].lay.wsb, st, gs[0]);
+    else if (b.meta_host)
+        r = tm_mul_packed_staged(reqs.data(), k, wss.data(), wsb.data(), meta, batch_guard_offset(),
+                                 b.meta_host, tm_batch_meta_bytes(kMaxBatch), st, gs.data());
+    else
+        r = tm_mul_packed(reqs.data(), k, wss.data(), wsb.data(), meta, batch_guard_offset(), st, gs.data());
     if (r != TM_OK) return r;
     // results: one copy per run of requests whose host buffers follow each
     // other (the device results of a batch are contiguous)
@@ -204,6 +220,18 @@ tm_status launch(tm_server* s, Batch& b)
             return TM_ERR_HIP;
         i = e;
     }
+    if (hipMemcpyAsync(b.guards_host, dg, k * sizeof(tm_guard), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return TM_ERR_HIP;
+    return TM_OK;
+}
+
+// Launch a batch: directly on its stream, or (graph mode) captured into a
+// HIP graph that is instantiated and launched as one unit.  A batch whose
+// capture fails (for instance pageable host buffers) is launched directly.
+tm_status launch(tm_server* s, Batch& b)
+{
+    hipStream_t st = s->streams[b.stream];
+    // host staging buffers are taken before any capture begins
     if (s->spare_guards.empty()) {
         void* h = nullptr;
         if (hipHostMalloc(&h, kMaxBatch * sizeof(tm_guard), hipHostMallocDefault) != hipSuccess) return TM_ERR_HIP;
@@ -211,8 +239,37 @@ tm_status launch(tm_server* s, Batch& b)
     }
     b.guards_host = s->spare_guards.back();
     s->spare_guards.pop_back();
-    if (hipMemcpyAsync(b.guards_host, dg, k * sizeof(tm_guard), hipMemcpyDeviceToHost, st) != hipSuccess)
-        return TM_ERR_HIP;
+    const size_t gmin = s->graphs == 1 ? 2 : s->graphs == 2 ? kGraphMinBatch : SIZE_MAX;
+    if (b.jobs.size() >= gmin) {
+        if (s->spare_meta.empty()) {
+            void* h = nullptr;
+            if (hipHostMalloc(&h, tm_batch_meta_bytes(kMaxBatch), hipHostMallocDefault) != hipSuccess)
+                return TM_ERR_HIP;
+            s->spare_meta.push_back(static_cast<char*>(h));
+        }
+        b.meta_host = s->spare_meta.back();
+        s->spare_meta.pop_back();
+        hipGraph_t g = nullptr;
+        bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            const tm_status r = enqueue(s, b, st);
+            ok = hipStreamEndCapture(st, &g) == hipSuccess && r == TM_OK && g;
+        }
+        if (ok) ok = hipGraphInstantiate(&b.graph, g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) (void)hipGraphDestroy(g);
+        if (ok) {
+            if (hipGraphLaunch(b.graph, st) != hipSuccess) return TM_ERR_HIP;
+        } else {
+            if (b.graph) (void)hipGraphExecDestroy(b.graph);
+            b.graph = nullptr;
+            (void)hipGetLastError();
+            const tm_status r = enqueue(s, b, st);
+            if (r != TM_OK) return r;
+        }
+    } else {
+        const tm_status r = enqueue(s, b, st);
+        if (r != TM_OK) return r;
+    }
     if (s->spare_events.empty()) {
         hipEvent_t e;
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return TM_ERR_HIP;
@@ -231,8 +288,12 @@ void release_batch(tm_server* s, Batch& b)
     s->pool.release(b.meta_off, batch_block_bytes());
     if (b.done) s->spare_events.push_back(b.done);
     if (b.guards_host) s->spare_guards.push_back(b.guards_host);
+    if (b.meta_host) s->spare_meta.push_back(b.meta_host);
+    if (b.graph) (void)hipGraphExecDestroy(b.graph);
     b.done = nullptr;
     b.guards_host = nullptr;
+    b.meta_host = nullptr;
+    b.graph = nullptr;
 }
 
 // Batches in flight per stream: one running and one queued behind it, so
@@ -437,17 +498,35 @@ void tm_server_destroy(tm_server* s)
         for (auto& b : q) {
             (void)hipEventDestroy(b.done);
             (void)hipHostFree(b.guards_host);
+            if (b.meta_host) (void)hipHostFree(b.meta_host);
+            if (b.graph) (void)hipGraphExecDestroy(b.graph);
         }
     for (auto e : s->spare_events) (void)hipEventDestroy(e);
     for (auto g : s->spare_guards) (void)hipHostFree(g);
+    for (auto m : s->spare_meta) (void)hipHostFree(m);
     for (auto st : s->streams) (void)hipStreamDestroy(st);
     if (s->base) (void)hipFree(s->base);
     delete s;
 }
 
+tm_status tm_server_use_graphs(tm_server* s, int mode)
+{
+    if (!s || mode < 0 || mode > 2) return TM_ERR_INVALID;
+    s->graphs = mode;
+    return TM_OK;
+}
+
 tm_status tm_serve_trace(const tm_request* reqs, const double* arrival_s, size_t count,
                          size_t pool_bytes, int n_streams, int max_inflight, double* latency_s,
                          tm_guard* guards_host, double* makespan_s)
+{
+    return tm_serve_trace_ex(reqs, arrival_s, count, pool_bytes, n_streams, max_inflight, latency_s,
+                             guards_host, makespan_s, 0);
+}
+
+tm_status tm_serve_trace_ex(const tm_request* reqs, const double* arrival_s, size_t count,
+                            size_t pool_bytes, int n_streams, int max_inflight, double* latency_s,
+                            tm_guard* guards_host, double* makespan_s, int flags)
 {
     if ((!reqs || !arrival_s || !latency_s) && count) return TM_ERR_INVALID;
     for (size_t i = 1; i < count; i++)
@@ -471,6 +550,7 @@ tm_status tm_serve_trace(const tm_request* reqs, const double* arrival_s, size_t
     tm_server* s = nullptr;
     tm_status r = tm_server_create(pool_bytes, n_streams, max_inflight, &s);
     if (r != TM_OK) return r;
+    s->graphs = (flags & TM_SERVE_GRAPHS_AUTO) ? 2 : (flags & TM_SERVE_GRAPHS) ? 1 : 0;
     std::map<uint64_t, size_t> index;
     std::vector<uint64_t> ids(64);
     std::vector<tm_status> sts(64);

@@ -292,7 +292,8 @@ bool launch_k1g_any(int kind, uint32_t L1, int fb, bool wide, const Group& g, ui
 }
 
 // Stages of one multiplication in launch order; the middle passes exist
-// only for three-pass splits.
+// only for three-pass splits, and fused plans have K0 in place of K1 and no
+// K2 or K3.
 enum Stage { ST_K1, ST_MIDF, ST_K2, ST_MIDI, ST_K3, ST_K4, ST_COUNT };
 
 // Kernel instance (key) and grid of request p at stage st; false if the
@@ -303,6 +304,14 @@ bool stage_shape(int st, int kind, const KParams& p, uint64_t& key, uint32_t& nx
     const int fb = fixed_b(kind, p) ? 1 : 0;
     const bool wide = wide_tiles(p);
     nx = ny = nz = 1;
+    if (p.fused) {
+        // K0: one workgroup per request
+        if (st == ST_K1) {
+            key = (1ull << 50) | ((uint64_t)kind << 40) | ((uint64_t)p.L1 << 16) | p.L2;
+            return true;
+        }
+        if (st != ST_K4) return false;
+    }
     switch (st) {
     case ST_K1:
         key = ((uint64_t)wide << 42) | ((uint64_t)kind << 40) | ((uint64_t)fb << 32) | p.L1;
@@ -397,6 +406,7 @@ struct Launch {
     int st;
     int kind, fb;
     bool wide;          // K1/K3: wide column tiles (three-pass split)
+    bool fused;         // K1 stage of a fused request: K0
     uint32_t a, b;      // instance: K1/K3 L1, K2 L2, middle Lm and W
     uint32_t ent0, nr;  // first table entry, requests
     uint32_t blocks;
@@ -467,6 +477,7 @@ void fill_params(const Plan& P, const uint64_t* u, const uint64_t* v, uint64_t* 
     p.ncoef = (uint32_t)P.ncoef;
     p.ncover = (uint32_t)P.ncover;
     p.nstatus = P.nstatus;
+    p.fused = P.fused ? 1u : 0u;
     p.invN = 1.0 / (double)P.N;
     p.invM = 1.0 / (double)P.M;
     fill_series(P, p);
@@ -527,7 +538,12 @@ tm_status plan_for(tm_kind kind, uint64_t n, Plan& P, int bt = 0, int bf = 0)
         if (e3 && *e3 == '1') flm |= SPLIT_ODD_ROW;
     }
     if (!flm) flm = tuned_split(kind, n);
-    if (!make_plan((int)kind, n, bt, bf, P, flm)) {
+    // fused small-size pass (K0) on request only (TM_FUSED=1): one
+    // workgroup per product is latency-bound and measured slower than the
+    // four-step kernels at these sizes
+    const char* fe = getenv("TM_FUSED");
+    const bool fused_ok = fe && *fe == '1';
+    if (!make_plan((int)kind, n, bt, bf, P, flm, false, false, fused_ok)) {
         g_last_error = "unsupported size";
         return TM_ERR_UNSUPPORTED;
     }
@@ -598,6 +614,19 @@ tm_status run(const Plan& P, uint64_t* w, const uint64_t* u, const uint64_t* v, 
     // FP64 path, or the FP32 path's double-float instances (P.df)
     int ne = 0;
     if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
+    if (P.fused) {
+        // small sizes: one workgroup per product does K1, K2 and K3
+        if (!launch_k0(P.kind, P.L1, P.L2, p, s)) {
+            g_last_error = "no fused kernel for the split";
+            return TM_ERR_UNSUPPORTED;
+        }
+        if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
+        if (mode == DIAG_RUN) launch_k4<true>(P.kind, p, s);
+        else launch_k4<false>(P.kind, p, s);
+        if (ev) HIP_TRY(hipEventRecord(ev[ne++], s));
+        HIP_TRY(hipGetLastError());
+        return TM_OK;
+    }
     if (!(P.df ? launch_k1_fp32c(P.kind, P.L1, p, s) : launch_k1_any(P.kind, p, s))) {
         g_last_error = "no kernel for L1";
         return TM_ERR_UNSUPPORTED;
@@ -641,7 +670,8 @@ tm_status run(const Plan& P, uint64_t* w, const uint64_t* u, const uint64_t* v, 
 }
 
 tm_status run_packed(const tm_request* reqs, size_t count, void* const* ws, const size_t* ws_bytes,
-                     tm_guard* const* guards, void* meta, size_t meta_bytes, hipStream_t s)
+                     tm_guard* const* guards, void* meta, size_t meta_bytes, hipStream_t s,
+                     void* host_staging = nullptr, size_t host_staging_bytes = 0)
 {
     if (count == 0) return TM_OK;
     if (!reqs || !ws || !ws_bytes || !meta) {
@@ -703,8 +733,10 @@ tm_status run_packed(const tm_request* reqs, size_t count, void* const* ws, cons
             L.kind = kinds[order[k].second];
             L.fb = fixed_b(L.kind, p0) ? 1 : 0;
             L.wide = wide_tiles(p0);
+            L.fused = p0.fused != 0;
             L.a = st == ST_K2 ? p0.L2 : (st == ST_MIDF || st == ST_MIDI) ? p0.Lm : p0.L1;
             L.b = (st == ST_MIDF || st == ST_MIDI) ? (uint32_t)mid_w(p0) : 0;
+            if (L.fused && st == ST_K1) L.b = p0.L2;  // K0 instance: (L1, L2)
             uint64_t blocks = 0;
             while (k < order.size() && order[k].first == key && L.nr < (uint32_t)GROUP_MAX) {
                 const uint32_t i = order[k].second;
@@ -724,11 +756,22 @@ tm_status run_packed(const tm_request* reqs, size_t count, void* const* ws, cons
             launches.push_back(L);
         }
     }
-    // one upload of parameters and tables through a pinned staging buffer
+    // one upload of parameters and tables through a pinned staging buffer:
+    // the caller's (which it keeps until the batch has run: safe under stream
+    // capture) or one of the library's, reused once its upload completed
     const size_t used = pbytes + ents.size() * sizeof(GroupEnt);
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
-    {
+    if (host_staging) {
+        if (host_staging_bytes < used) {
+            g_last_error = "host staging buffer too small";
+            return TM_ERR_INVALID;
+        }
+        char* h = static_cast<char*>(host_staging);
+        memcpy(h, ps.data(), count * sizeof(KParams));
+        memcpy(h + pbytes, ents.data(), ents.size() * sizeof(GroupEnt));
+        HIP_TRY(hipMemcpyAsync(meta, h, used, hipMemcpyHostToDevice, s));
+    } else {
         std::lock_guard<std::mutex> lk(g_stage_mu);
         StageBuf* sb = nullptr;
         tm_status st = stage_acquire(dev, used, sb);
@@ -745,7 +788,10 @@ tm_status run_packed(const tm_request* reqs, size_t count, void* const* ws, cons
         const Group g{dps, dent + L.ent0, L.nr};
         bool ok = true;
         switch (L.st) {
-        case ST_K1: ok = launch_k1g_any(L.kind, L.a, L.fb, L.wide, g, L.blocks, s); break;
+        case ST_K1:
+            ok = L.fused ? launch_k0g(L.kind, L.a, L.b, g, L.blocks, s)
+                         : launch_k1g_any(L.kind, L.a, L.fb, L.wide, g, L.blocks, s);
+            break;
         case ST_MIDF: ok = launch_midg<false>(L.a, (int)L.b, g, L.blocks, s); break;
         case ST_K2: ok = launch_k2g(L.a, g, L.blocks, s); break;
         case ST_MIDI: ok = launch_midg<true>(L.a, (int)L.b, g, L.blocks, s); break;
@@ -802,6 +848,8 @@ void fill_info(tm_kind kind, uint64_t n_bits, const Plan& P, tm_plan_info* out)
     out->Lm = P.Lm;
     out->rounding_bound = rounding_bound(P);
     out->guaranteed = out->rounding_bound <= GUARANTEED_MAX ? 1u : 0u;
+    out->fused = P.fused ? 1u : 0u;
+    out->reserved = 0;
 }
 
 // ------------------------------------------------------------ static scratch
@@ -1127,6 +1175,19 @@ tm_status tm_mul_packed(const tm_request* reqs, size_t count, void* const* works
     return run_packed(reqs, count, workspaces, workspace_bytes, guards_dev, meta, meta_bytes, stream);
 }
 
+tm_status tm_mul_packed_staged(const tm_request* reqs, size_t count, void* const* workspaces,
+                               const size_t* workspace_bytes, void* meta, size_t meta_bytes,
+                               void* host_staging, size_t host_staging_bytes, hipStream_t stream,
+                               tm_guard* const* guards_dev)
+{
+    if (count && !host_staging) {
+        g_last_error = "null host staging buffer";
+        return TM_ERR_INVALID;
+    }
+    return run_packed(reqs, count, workspaces, workspace_bytes, guards_dev, meta, meta_bytes, stream,
+                      host_staging, host_staging_bytes);
+}
+
 tm_status tm_mul_batched(const tm_request* reqs, size_t count, void* workspace,
                          size_t workspace_bytes, hipStream_t stream, tm_guard* guards_dev)
 {
@@ -1234,8 +1295,9 @@ tm_status tm_profile_stages(tm_kind kind, uint64_t* w, const uint64_t* u, const 
     Plan P;
     tm_status st = plan_for(kind, n_bits, P);
     if (st != TM_OK) return st;
-    const int ns = P.Lm > 1 ? 6 : 4;
-    const char** nm = P.Lm > 1 ? kNames3 : kNames2;
+    static const char* kNamesF[2] = {"fused_fft", "backmap_round_carry"};
+    const int ns = P.fused ? 2 : P.Lm > 1 ? 6 : 4;
+    const char** nm = P.fused ? kNamesF : P.Lm > 1 ? kNames3 : kNames2;
     hipEvent_t ev[7];
     for (int i = 0; i <= ns; i++) HIP_TRY(hipEventCreate(&ev[i]));
     st = run(P, w, u, v, workspace, workspace_bytes, stream, nullptr, RUN, nullptr, nullptr, ev);

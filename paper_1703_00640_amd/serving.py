@@ -40,11 +40,12 @@ class Mix:
         return sum(n for _, n in self.mix)
 
 
-def run(mix, arrival_s, pool_bytes=1 << 30, n_streams=4, max_inflight=0):
-    """Replay ``arrival_s`` over a Mix; returns a dict of statistics and the
-    per-request latencies and guards."""
+def run(mix, arrival_s, pool_bytes=1 << 30, n_streams=4, max_inflight=0, graphs=False):
+    """Replay ``arrival_s`` over a Mix (graphs: batches as captured HIP
+    graphs); returns a dict of statistics and the per-request latencies and
+    guards."""
     lat, guards, makespan = serve_trace(mix.requests, arrival_s, pool_bytes, n_streams,
-                                        max_inflight)
+                                        max_inflight, graphs)
     lat = np.array(lat)
     ok = lat >= 0
     return {

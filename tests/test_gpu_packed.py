@@ -135,6 +135,25 @@ def test_packed_single_empty_and_tiny():
                            ("hi", 1 << 15)], seed=950))
 
 
+def test_packed_fused_small_pass(monkeypatch):
+    """A packed batch of small requests with the fused small-size pass on
+    (TM_FUSED=1: one K0 workgroup per request, then K4) equals the
+    four-step products, request by request, and the oracle."""
+    mix = [("lo", 5000), ("hi", 20000), ("full", 3000), ("lo", 1 << 16), ("hi", 1 << 16),
+           ("full", 1 << 16), ("hi", 89000), ("lo", 1100)]
+    want = [r[4] for r in run_batch(mix, seed=960)]
+    monkeypatch.setenv("TM_FUSED", "1")
+    tm = _tm()
+    say("[packed fused]", [(k, n, tm.plan(k, n)["fused"]) for k, n in mix])
+    assert sum(tm.plan(k, n)["fused"] for k, n in mix) >= 6
+    res = run_batch(mix, seed=960)
+    for i, (k, n, u, v, w, g, du, dv) in enumerate(res):
+        assert g.flags == 0
+        assert np.array_equal(w, want[i]), "request %d (%s, n=%d) fused differs" % (i, k, n)
+        check_oracle(k, u, v, n, w)
+    monkeypatch.delenv("TM_FUSED")
+
+
 def test_graph_capture_replays_match_eager():
     """tm_mul captured into a HIP graph (torch stream capture) after
     tm_prepare: every replay, with new operands copied in eagerly between

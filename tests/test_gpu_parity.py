@@ -446,6 +446,35 @@ def test_odd_factor_in_rows(monkeypatch, n, lm):
             assert oracle.hi_accepts(w, q, nz)
 
 
+@pytest.mark.parametrize("n", [1, 700, 1025, 4096, 20000, 1 << 16, 70000, 89000])
+def test_fused_small_pass_matches_four_step(monkeypatch, n):
+    """The fused small-size pass K0 (whole transform of a product in one
+    workgroup's LDS, M <= 4096; on request with TM_FUSED=1) followed by K4,
+    against the four-step kernels and the oracle: same bits for every kind
+    (same plan, same exact rounded coefficients), squares included."""
+    tm = _tm()
+    u, v = inputs.operand_pair(n, 140 + n % 11)
+    four = {}
+    for kind in ("lo", "hi", "full"):
+        assert tm.plan(kind, n)["fused"] == 0
+        four[kind] = run_kind(kind, u, v, n)[0]
+    check_all(u, v, n)
+    monkeypatch.setenv("TM_FUSED", "1")
+    fused = {kind: tm.plan(kind, n)["fused"] for kind in ("lo", "hi", "full")}
+    say("[fused] n=%d fused %s" % (n, fused))
+    assert any(fused.values())
+    for kind in ("lo", "hi", "full"):
+        w, g = run_kind(kind, u, v, n)
+        assert g.flags == 0
+        assert np.array_equal(w, four[kind]), kind
+    du = to_dev(u)
+    for kind in ("lo", "full"):
+        sq = to_host(tm.mul(kind, du, du, n))
+        want = oracle.mul_lo(u, u, n) if kind == "lo" else oracle.mul_full(u, u, n)
+        assert np.array_equal(sq, want), kind
+    monkeypatch.delenv("TM_FUSED")
+
+
 def test_config_n2_26_parity():
     """n = 2^26 (three-pass split chosen automatically): lo, hi, full vs the
     oracle."""

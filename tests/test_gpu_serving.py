@@ -65,6 +65,44 @@ def test_same_alone_and_in_the_mix():
             check_oracle(k, u, v, n, w)
 
 
+def test_config_range_alone_and_in_the_mix():
+    """The serving workload's full size range, n log-uniform over [2^12,
+    2^22] bits with all three kinds: every request equals its result alone,
+    and every third one (all kinds, up to the largest sizes) the oracle."""
+    from paper_1703_00640_amd import serving
+    mix = inputs.serving_mix(64, seed=31, log2_lo=12, log2_hi=22)
+    say("serving mix: 64 requests, n in [2^12, 2^22], largest %d" % max(n for _, n in mix))
+    m = serving.Mix(mix, seed=32)
+    arr = inputs.poisson_arrivals(len(mix), rate=5e4, seed=33)
+    stats, lat, guards = serving.run(m, arr, pool_bytes=256 << 20, n_streams=4)
+    say("served", stats)
+    assert stats["failed"] == 0 and stats["guard_flags"] == 0
+    for i, (k, n) in enumerate(mix):
+        u, v = m.operands(i)
+        w = m.result(i)
+        assert np.array_equal(w, alone(k, u, v, n)), "request %d (%s, n=%d) differs alone" % (i, k, n)
+        if i % 3 == 0:
+            check_oracle(k, u, v, n, w)
+
+
+def test_graph_mode_same_results():
+    """Batches captured into HIP graphs (server graph mode) give the same
+    results as alone, over a mix with multi-request batches."""
+    from paper_1703_00640_amd import serving
+    mix = inputs.serving_mix(48, seed=41, log2_lo=12, log2_hi=20)
+    m = serving.Mix(mix, seed=42)
+    stats, lat, guards = serving.run(m, np.zeros(len(mix)), pool_bytes=256 << 20, n_streams=2,
+                                     graphs=True)
+    say("graph mode", stats)
+    assert stats["failed"] == 0 and stats["guard_flags"] == 0
+    for i, (k, n) in enumerate(mix):
+        u, v = m.operands(i)
+        w = m.result(i)
+        assert np.array_equal(w, alone(k, u, v, n)), "request %d (%s, n=%d) differs alone" % (i, k, n)
+        if i % 4 == 0:
+            check_oracle(k, u, v, n, w)
+
+
 def test_server_submit_poll_and_small_pool():
     """Incremental API with a pool that holds about two of the largest
     requests: admission waits for memory, results stay exact, with pinned
