@@ -322,17 +322,36 @@ __device__ __forceinline__ C tw_half(const C* twl, int e)
 #endif
 constexpr bool TW_DIRECT = TM_TW_DIRECT != 0;
 
-// One Stockham stage of radix R after NS points have been combined.
-template <int P, int R, int NS, int NB, int NT, bool INV, bool COLS, int RS, int PS, typename C>
+// Synchronisation between the read and write halves of a stage and between
+// stages: the whole workgroup, or (WAVE) only the wavefront that owns the
+// tile.  A wavefront's LDS operations execute in program order, so a tile
+// transformed by one wavefront needs no hardware barrier: the fences keep
+// the compiler from moving LDS accesses across the stage boundary.
+template <bool WAVE>
+__device__ __forceinline__ void stage_sync()
+{
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// One Stockham stage of radix R after NS points have been combined.  WAVE:
+// the tile belongs to one wavefront (NT = 64, lanes as threads).
+template <int P, int R, int NS, int NB, int NT, bool INV, bool COLS, int RS, int PS, bool WAVE, typename C>
 __device__ __forceinline__ void fft_stage(C* buf, const C* twl)
 {
+    static_assert(!WAVE || NT == 64, "a wavefront tile has 64 threads");
     constexpr int BF = P / R;
     constexpr int TOT = BF * NB;
     constexpr int PER = (TOT + NT - 1) / NT;
     constexpr uint32_t ESTEP = P / (NS * R);
     C v[PER][R];
     int jj[PER], cc[PER];
-    const int tid = threadIdx.x;
+    const int tid = WAVE ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
 #pragma unroll
     for (int q = 0; q < PER; q++) {
         int idx = tid + q * NT;
@@ -343,7 +362,7 @@ __device__ __forceinline__ void fft_stage(C* buf, const C* twl)
             for (int r = 0; r < R; r++) v[q][r] = buf[tile_addr<COLS, NB, RS, PS>(jj[q] + r * BF, cc[q])];
         }
     }
-    __syncthreads();
+    stage_sync<WAVE>();
 #pragma unroll
     for (int q = 0; q < PER; q++) {
         int idx = tid + q * NT;
@@ -373,26 +392,27 @@ __device__ __forceinline__ void fft_stage(C* buf, const C* twl)
             for (int r = 0; r < R; r++) buf[tile_addr<COLS, NB, RS, PS>(out + r * NS, cc[q])] = v[q][r];
         }
     }
-    __syncthreads();
+    stage_sync<WAVE>();
 }
 
-template <int P, int NS, int NB, int NT, bool INV, bool COLS, int RS, int PS, typename C>
+template <int P, int NS, int NB, int NT, bool INV, bool COLS, int RS, int PS, bool WAVE, typename C>
 __device__ __forceinline__ void fft_stages(C* buf, const C* twl)
 {
     if constexpr (NS < P) {
         constexpr int R = pick_radix(P / NS);
-        fft_stage<P, R, NS, NB, NT, INV, COLS, RS, PS>(buf, twl);
-        fft_stages<P, NS * R, NB, NT, INV, COLS, RS, PS>(buf, twl);
+        fft_stage<P, R, NS, NB, NT, INV, COLS, RS, PS, WAVE>(buf, twl);
+        fft_stages<P, NS * R, NB, NT, INV, COLS, RS, PS, WAVE>(buf, twl);
     }
 }
 
 // In-place DFT of NB sequences of length P in LDS; twl is an LDS table of
 // exp(-2 pi i e / P), e < P.  Caller must __syncthreads() before (data and
 // table written); the routine ends with a barrier.
-template <int P, int NB, int NT, bool INV, bool COLS, int RS = P, int PS = TM_PAD_SHIFT, typename C>
+template <int P, int NB, int NT, bool INV, bool COLS, int RS = P, int PS = TM_PAD_SHIFT, bool WAVE = false,
+          typename C>
 __device__ __forceinline__ void tile_fft(C* buf, const C* twl)
 {
-    fft_stages<P, 1, NB, NT, INV, COLS, RS, PS>(buf, twl);
+    fft_stages<P, 1, NB, NT, INV, COLS, RS, PS, WAVE>(buf, twl);
 }
 
 // Copy the sub-transform table into LDS: the first half only when P is even

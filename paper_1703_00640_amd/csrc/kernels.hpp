@@ -24,7 +24,8 @@
 // TM_NT2, TM_NT3, TM_NT4, TM_NTM threads per workgroup of K1, K2, K3, K4 and
 // the middle pass; TM_TILE1 / TM_TILE3 complex elements per K1 / K3 column
 // tile; TM_DPT coefficients per K4 thread; TM_PAD_SHIFT LDS tile padding
-// (TM_PAD_K2 for K2's row tiles).
+// (TM_PAD_K2 for K2's row tiles); TM_K2_WAVE wavefront-owned 1024-point K2
+// rows; TM_K4_WAVES K4's register bound.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -52,6 +53,13 @@ constexpr int LMAX = 9;         // largest supported series length lambda
 #define TM_PAD_K2 5
 #endif
 constexpr int PAD2 = TM_PAD_K2;  // K2 row tiles: one pad element per 32 (measured best)
+#ifndef TM_K2_WAVE
+#define TM_K2_WAVE 1
+#endif
+// K2 row transforms of 1024 points: one wavefront per row (measured 3%
+// faster there; slower for 384- and 768-point rows, which keep the
+// workgroup-wide transform)
+constexpr bool K2_WAVE = TM_K2_WAVE != 0;
 #ifndef TM_NT3
 #define TM_NT3 256
 #endif
@@ -785,7 +793,16 @@ __device__ __forceinline__ void k2_body(const KParams& p, const Blk bk)
         }
     }
     __syncthreads();
-    tile_fft<L2, 4, NT2, false, false, L2, PAD2>(rows, twl);
+    // forward row DFTs of the four rows: one wavefront per row (no
+    // workgroup barriers inside the transforms), or the whole workgroup
+    constexpr bool WAVE_ROWS = K2_WAVE && NT2 == 256 && L2 == 1024;
+    static_assert(!WAVE_ROWS || L2 % (1 << PAD2) == 0, "a row starts on a pad boundary");
+    if constexpr (WAVE_ROWS) {
+        tile_fft<L2, 1, 64, false, false, L2, PAD2, true>(rows + pidx<PAD2>((int)(threadIdx.x >> 6) * L2), twl);
+        __syncthreads();
+    } else {
+        tile_fft<L2, 4, NT2, false, false, L2, PAD2>(rows, twl);
+    }
 
     constexpr int PER = (2 * L2 + NT2 - 1) / NT2;
     const C wrow0 = to_elem<C>(cmul(wr0a, wr0b)), wrow1 = to_elem<C>(cmul(wr1a, wr1b));
@@ -815,7 +832,13 @@ __device__ __forceinline__ void k2_body(const KParams& p, const Blk bk)
     }
     __syncthreads();
     // inverse row DFTs of rows 0 and 2 (row stride 2*L2)
-    tile_fft<L2, 2, NT2, true, false, 2 * L2, PAD2>(rows, twl);
+    if constexpr (WAVE_ROWS) {
+        const int w = (int)(threadIdx.x >> 6);
+        if (w < 2) tile_fft<L2, 1, 64, true, false, L2, PAD2, true>(rows + pidx<PAD2>(2 * w * L2), twl);
+        __syncthreads();
+    } else {
+        tile_fft<L2, 2, NT2, true, false, 2 * L2, PAD2>(rows, twl);
+    }
     for (int e = threadIdx.x; e < 2 * L2; e += NT2) {
         const int pr = e / L2, j2 = e % L2;
         if (pr == 1 && rowb == rowa) continue;
