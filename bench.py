@@ -214,7 +214,9 @@ def serving_bench(count=4096, n_streams=4):
 def small_latency_bench(log2n=16, reps=200):
     """One small multiplication at a time (n = 2^16, the smallest benchmark
     size): microseconds per call for back-to-back eager calls (launch-bound
-    at this size) and for replays of the same call captured in a HIP graph."""
+    at this size) and for replays of the same call captured in a HIP graph;
+    then 256 such products of one kind in packed launches, microseconds of
+    GPU time per product."""
     import torch
     import paper_1703_00640_amd as tm
     from paper_1703_00640_amd import inputs
@@ -253,6 +255,28 @@ def small_latency_bench(log2n=16, reps=200):
             torch.cuda.synchronize()
             res[name][k] = round(e0.elapsed_time(e1) * 1e3 / reps, 2)
         del graph
+    # many small products in packed launches (tm_mul_batched: one launch per
+    # stage for the whole batch), GPU time per product
+    nb, breps = 256, 20
+    pool_u = torch.from_numpy(inputs.operand_pair(n * nb, 3)[0].view(np.int64)).to(dev)
+    pool_v = torch.from_numpy(inputs.operand_pair(n * nb, 4)[0].view(np.int64)).to(dev)
+    res["batched_us_per_product"] = {"batch": nb}
+    for k in ("lo", "hi", "full"):
+        nout = 2 * L if k == "full" else L
+        outs = torch.empty(nb * nout, dtype=torch.int64, device=dev)
+        reqs = [(k, pool_u[i * L:(i + 1) * L], pool_v[i * L:(i + 1) * L], n, outs[i * nout:(i + 1) * nout])
+                for i in range(nb)]
+        ws = torch.empty(tm.workspace_bytes_batched(reqs), dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            tm.mul_batched(reqs, workspace=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(breps):
+            tm.mul_batched(reqs, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        res["batched_us_per_product"][k] = round(e0.elapsed_time(e1) * 1e3 / (breps * nb), 3)
     return res
 
 

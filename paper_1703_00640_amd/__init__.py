@@ -288,15 +288,8 @@ def mul_full(u, v, n_bits, **kw):
     return mul("full", u, v, n_bits, **kw)
 
 
-def mul_batched(requests, workspace=None, stream=None, guards=None):
-    """requests: list of (kind, u, v, n_bits, out) with device tensors of
-    independent multiplications; runs them on one stream in packed launches
-    (one launch per stage and kernel instance), each request with its own
-    slice of one workspace."""
-    if not requests:
-        return
+def _request_array(requests):
     arr = (_Request * len(requests))()
-    dev = requests[0][1].device
     for i, (kind, u, v, n_bits, out) in enumerate(requests):
         L = nlimbs(n_bits)
         k = _kind(kind)
@@ -305,6 +298,26 @@ def mul_batched(requests, workspace=None, stream=None, guards=None):
         arr[i].u = _dev_ptr(u, L, "u").value
         arr[i].v = _dev_ptr(v, L, "v").value
         arr[i].w = _dev_ptr(out, 2 * L if k == 0 else L, "out").value
+    return arr
+
+
+def workspace_bytes_batched(requests):
+    """Workspace bytes of mul_batched for ``requests`` (tm_workspace_bytes_batched)."""
+    nb = _load().tm_workspace_bytes_batched(ctypes.byref(_request_array(requests)), len(requests))
+    if nb == 0:
+        raise TmulError("unsupported request in batch")
+    return nb
+
+
+def mul_batched(requests, workspace=None, stream=None, guards=None):
+    """requests: list of (kind, u, v, n_bits, out) with device tensors of
+    independent multiplications; runs them on one stream in packed launches
+    (one launch per stage and kernel instance), each request with its own
+    slice of one workspace."""
+    if not requests:
+        return
+    arr = _request_array(requests)
+    dev = requests[0][1].device
     lib = _load()
     nb = lib.tm_workspace_bytes_batched(ctypes.byref(arr), len(requests))
     if nb == 0:
