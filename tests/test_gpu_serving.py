@@ -85,14 +85,18 @@ def test_config_range_alone_and_in_the_mix():
             check_oracle(k, u, v, n, w)
 
 
-def test_graph_mode_same_results():
-    """Batches captured into HIP graphs (server graph mode) give the same
-    results as alone, over a mix with multi-request batches."""
+@pytest.mark.parametrize("graphs", [True, "auto"])
+def test_graph_mode_same_results(graphs):
+    """Batches captured into HIP graphs (server graph mode 1: every batch of
+    two or more; "auto": batches of 16 or more) give the same results as
+    alone, over the serving workload's size range with multi-request
+    batches."""
     from paper_1703_00640_amd import serving
-    mix = inputs.serving_mix(48, seed=41, log2_lo=12, log2_hi=20)
+    mix = inputs.serving_mix(48, seed=41, log2_lo=12, log2_hi=22)
+    say("graph mode %s: 48 requests, n in [2^12, 2^22]" % graphs)
     m = serving.Mix(mix, seed=42)
     stats, lat, guards = serving.run(m, np.zeros(len(mix)), pool_bytes=256 << 20, n_streams=2,
-                                     graphs=True)
+                                     graphs=graphs)
     say("graph mode", stats)
     assert stats["failed"] == 0 and stats["guard_flags"] == 0
     for i, (k, n) in enumerate(mix):
