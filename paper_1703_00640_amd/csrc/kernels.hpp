@@ -1168,7 +1168,10 @@ __device__ __forceinline__ CarryF compose(CarryF f, CarryF g)
 __device__ __forceinline__ int64_t apply(CarryF f, int64_t c) { return f.A + (c >= f.T ? 1 : 0); }
 
 // Look-back records are 64-bit words holding a 2-bit state (0 empty,
-// 1 aggregate, 2 inclusive) and a 62-bit two's-complement value.  Each word
+// 1 aggregate, 2 inclusive, 3 constant aggregate) and a 62-bit
+// two's-complement value.  A constant aggregate (almost every workgroup's,
+// since one constant limb function makes the composition constant) is one
+// word holding its carry-out, so a reader needs no second load.  Each word
 // is written once per state by a single relaxed device-scope atomic store
 // and polled with relaxed device-scope atomic loads: no acquire/release
 // fences, which on this GPU would write back or invalidate the whole L2.
@@ -1538,8 +1541,9 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
     // the guard's global atomics go out from wave 1 while wave 0 looks back
     if (wv == 1 && lane == 0) publish_guard();
 
-    // decoupled look-back, one wavefront.  status[2g] = state | A (aggregate)
-    // or state | C (inclusive carry-out), status[2g+1] = state | T.  Values
+    // decoupled look-back, one wavefront.  status[2g] = state | A (aggregate),
+    // state | C (inclusive or constant aggregate: the carry-out), and for a
+    // non-constant aggregate status[2g+1] = state | T.  Values
     // are carries (|c| < 2^53) and thresholds clamped to +-2^61, which act
     // as +-infinity for such carries.
     if (wv == 0) {
@@ -1549,8 +1553,12 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
         int64_t cin = 0;
         if (g > 0) {
             if (lane == 0) {
-                st_rlx(&st[2 * g + 1], pack62(1, agg.T));
-                st_rlx(&st[2 * g + 0], pack62(1, agg.A));
+                if (agg.T == INT64_MAX || agg.T == INT64_MIN) {
+                    st_rlx(&st[2 * g + 0], pack62(3, apply(agg, 0)));
+                } else {
+                    st_rlx(&st[2 * g + 1], pack62(1, agg.T));
+                    st_rlx(&st[2 * g + 0], pack62(1, agg.A));
+                }
             }
             CarryF acc = {0, INT64_MAX};
             bool have_acc = false;
@@ -1570,7 +1578,7 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
                 if (idx >= 0) {
                     const uint64_t wa = ld_rlx(&st[2 * idx]);
                     const uint64_t sa = wa >> 62;
-                    if (sa == 2) {
+                    if (sa >= 2) {  // inclusive, or constant aggregate: the carry-out
                         fv.A = unpack62(wa);
                     } else if (sa == 1) {
                         const uint64_t wt = ld_rlx(&st[2 * idx + 1]);
@@ -1597,16 +1605,23 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
                     __builtin_amdgcn_s_sleep(2);
                     continue;
                 }
-                if (ma && lane < top) fv = CarryF{0, INT64_MAX};  // absorbed: any constant
-                // ordered reduction: lane 0 ends with f_(idx 63) o ... o f_(idx 0)
-                CarryF r = fv;
+                CarryF r;
+                if (ma >> 63) {
+                    // the nearest record (the usual case) fixes the carry
+                    r.A = __shfl(fv.A, 63);
+                    r.T = __shfl(fv.T, 63);
+                } else {
+                    if (ma && lane < top) fv = CarryF{0, INT64_MAX};  // absorbed: any constant
+                    // ordered reduction: lane 0 ends with f_(idx 63) o ... o f_(idx 0)
+                    r = fv;
 #pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const int64_t oa = __shfl_down(r.A, d), ot = __shfl_down(r.T, d);
-                    if ((lane & (2 * d - 1)) == 0) r = compose(r, CarryF{oa, ot});
+                    for (int d = 1; d < 64; d <<= 1) {
+                        const int64_t oa = __shfl_down(r.A, d), ot = __shfl_down(r.T, d);
+                        if ((lane & (2 * d - 1)) == 0) r = compose(r, CarryF{oa, ot});
+                    }
+                    r.A = __shfl(r.A, 0);
+                    r.T = __shfl(r.T, 0);
                 }
-                r.A = __shfl(r.A, 0);
-                r.T = __shfl(r.T, 0);
                 const CarryF tot = have_acc ? compose(r, acc) : r;
                 // done at an absorbing record, or as soon as the carry no
                 // longer depends on what lies further back (constant function)
