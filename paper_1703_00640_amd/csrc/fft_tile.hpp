@@ -405,6 +405,86 @@ __device__ __forceinline__ void fft_stages(C* buf, const C* twl)
     }
 }
 
+// Exchange of FP64 complex values between lanes of a wavefront, one 32-bit
+// word at a time: HALVES swaps lanes 32..63 of a with lanes 0..31 of b
+// (permlane32_swap), otherwise the odd 16-lane rows of a with the even rows
+// of b (permlane16_swap).
+template <bool HALVES>
+__device__ __forceinline__ void lane_swap(double2& a, double2& b)
+{
+    uint32_t wa[4], wb[4];
+    __builtin_memcpy(wa, &a, 16);
+    __builtin_memcpy(wb, &b, 16);
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        if constexpr (HALVES) {
+            const auto r = __builtin_amdgcn_permlane32_swap(wa[i], wb[i], false, false);
+            wa[i] = r[0];
+            wb[i] = r[1];
+        } else {
+            const auto r = __builtin_amdgcn_permlane16_swap(wa[i], wb[i], false, false);
+            wa[i] = r[0];
+            wb[i] = r[1];
+        }
+    }
+    __builtin_memcpy(&a, wa, 16);
+    __builtin_memcpy(&b, wb, 16);
+}
+
+// 1024-point DFT of one LDS row by one wavefront, stages of radix 16, 16
+// and 4.  The first exchange goes through LDS; the last stays in registers.
+// After the second stage lane (a, k) = 16 a + k holds points 256 a + k +
+// 16 r, r < 16, and the third stage's butterfly k + 16 r takes point r of
+// the four lanes (a, k), a < 4: a 4 x 4 transpose of register blocks
+// across the lane rows (permlane swaps on lane bit 5, then bit 4) gives
+// lane (a, k) the inputs of butterflies k + 16 (4 q + a), q < 4.
+template <bool INV, int PS>
+__device__ __forceinline__ void row1024_wave(double2* buf, const double2* twl)
+{
+    constexpr int P = 1024;
+    fft_stage<P, 16, 1, 1, 64, INV, false, P, PS, true>(buf, twl);
+    const int lane = (int)(threadIdx.x & 63);
+    const int k = lane & 15, a = lane >> 4;
+    double2 y[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) y[r] = buf[pidx<PS>(lane + 64 * r)];
+    if (k != 0) {
+        const double2 w1 = tw_half<P>(twl, k * 4);
+        double2 pw[16];
+        tw_powers<16>(INV ? cconj(w1) : w1, pw);
+#pragma unroll
+        for (int r = 1; r < 16; r++) y[r] = cmul(y[r], pw[r]);
+    }
+    dftR<16, INV>(y);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        lane_swap<true>(y[4 * q], y[4 * q + 2]);
+        lane_swap<true>(y[4 * q + 1], y[4 * q + 3]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        lane_swap<false>(y[4 * q], y[4 * q + 1]);
+        lane_swap<false>(y[4 * q + 2], y[4 * q + 3]);
+    }
+    stage_sync<true>();  // every read of the row precedes the writes below
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int j = k + 64 * q + 16 * a;
+        double2* x = y + 4 * q;
+        if (j != 0) {
+            const double2 w1 = tw_half<P>(twl, j);
+            double2 pw[4];
+            tw_powers<4>(INV ? cconj(w1) : w1, pw);
+#pragma unroll
+            for (int e = 1; e < 4; e++) x[e] = cmul(x[e], pw[e]);
+        }
+        dftR<4, INV>(x);
+#pragma unroll
+        for (int e = 0; e < 4; e++) buf[pidx<PS>(j + 256 * e)] = x[e];
+    }
+    stage_sync<true>();
+}
+
 // In-place DFT of NB sequences of length P in LDS; twl is an LDS table of
 // exp(-2 pi i e / P), e < P.  Caller must __syncthreads() before (data and
 // table written); the routine ends with a barrier.

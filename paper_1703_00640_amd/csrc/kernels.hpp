@@ -25,10 +25,13 @@
 // the middle pass; TM_TILE1 / TM_TILE3 complex elements per K1 / K3 column
 // tile; TM_DPT coefficients per K4 thread; TM_PAD_SHIFT LDS tile padding
 // (TM_PAD_K2 for K2's row tiles); TM_K2_WAVE wavefront-owned 1024-point K2
-// rows; TM_K4_WAVES K4's register bound.
+// rows, TM_K2_SHUFFLE their last exchange by lane swaps; TM_K4_WAVES K4's
+// register bound.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "fft_tile.hpp"
 #include "tmul.h"
@@ -60,6 +63,12 @@ constexpr int PAD2 = TM_PAD_K2;  // K2 row tiles: one pad element per 32 (measur
 // faster there; slower for 384- and 768-point rows, which keep the
 // workgroup-wide transform)
 constexpr bool K2_WAVE = TM_K2_WAVE != 0;
+#ifndef TM_K2_SHUFFLE
+#define TM_K2_SHUFFLE 1
+#endif
+// wavefront-owned 1024-point rows: the last Stockham exchange by lane swaps
+// instead of LDS (FP64 tiles; full product's K2 at n = 2^30 2% faster)
+constexpr bool K2_SHUFFLE = TM_K2_SHUFFLE != 0;
 #ifndef TM_NT3
 #define TM_NT3 256
 #endif
@@ -798,7 +807,11 @@ __device__ __forceinline__ void k2_body(const KParams& p, const Blk bk)
     constexpr bool WAVE_ROWS = K2_WAVE && NT2 == 256 && L2 == 1024;
     static_assert(!WAVE_ROWS || L2 % (1 << PAD2) == 0, "a row starts on a pad boundary");
     if constexpr (WAVE_ROWS) {
-        tile_fft<L2, 1, 64, false, false, L2, PAD2, true>(rows + pidx<PAD2>((int)(threadIdx.x >> 6) * L2), twl);
+        C* row = rows + pidx<PAD2>((int)(threadIdx.x >> 6) * L2);
+        if constexpr (K2_SHUFFLE && std::is_same<C, double2>::value)
+            row1024_wave<false, PAD2>(row, twl);
+        else
+            tile_fft<L2, 1, 64, false, false, L2, PAD2, true>(row, twl);
         __syncthreads();
     } else {
         tile_fft<L2, 4, NT2, false, false, L2, PAD2>(rows, twl);
@@ -834,7 +847,13 @@ __device__ __forceinline__ void k2_body(const KParams& p, const Blk bk)
     // inverse row DFTs of rows 0 and 2 (row stride 2*L2)
     if constexpr (WAVE_ROWS) {
         const int w = (int)(threadIdx.x >> 6);
-        if (w < 2) tile_fft<L2, 1, 64, true, false, L2, PAD2, true>(rows + pidx<PAD2>(2 * w * L2), twl);
+        if (w < 2) {
+            C* row = rows + pidx<PAD2>(2 * w * L2);
+            if constexpr (K2_SHUFFLE && std::is_same<C, double2>::value)
+                row1024_wave<true, PAD2>(row, twl);
+            else
+                tile_fft<L2, 1, 64, true, false, L2, PAD2, true>(row, twl);
+        }
         __syncthreads();
     } else {
         tile_fft<L2, 2, NT2, true, false, 2 * L2, PAD2>(rows, twl);
