@@ -487,6 +487,8 @@ def step_bench(tm, torch, n, steps, warmup, stage_reps, tag):
     gd = {k: tm.read_guard(guards[k]).as_dict() for k in kinds}
     per = {k: timed(lambda k=k: one(k), steps) for k in kinds}
     per_sq = {k: timed(lambda k=k: one(k, du, du), steps) for k in kinds}
+    # one call at a time (each bracketed by its own events): median, p10, p90
+    calls = {k: [timed(lambda k=k: one(k), 1) for _ in range(steps)] for k in kinds}
     for k in kinds:
         g = tm.read_guard(guards[k])
         if g.flags or g.max_dist >= 0.25:
@@ -509,6 +511,11 @@ def step_bench(tm, torch, n, steps, warmup, stage_reps, tag):
         "ratio_lo_full": round(per["lo"] / per["full"], 4),
         "ratio_hi_full": round(per["hi"] / per["full"], 4),
         "square_ms": {k: round(per_sq[k], 5) for k in kinds},
+        "call_ms": {k: {"median": round(float(np.median(calls[k])), 5),
+                        "p10": round(float(np.percentile(calls[k], 10)), 5),
+                        "p90": round(float(np.percentile(calls[k], 90)), 5)} for k in kinds},
+        "ratio_median_lo_full": round(float(np.median(calls["lo"]) / np.median(calls["full"])), 4),
+        "ratio_median_hi_full": round(float(np.median(calls["hi"]) / np.median(calls["full"])), 4),
         "stage_ms": {k: {s_: round(t, 5) for s_, t in stage[k].items()} for k in kinds},
         "stage_gb_s": {k: {nm: round(nbytes[k][nm] / (t * 1e-3) / 1e9, 1) for nm, t in stage[k].items()}
                        for k in kinds},
