@@ -59,7 +59,7 @@ constexpr int PAD2 = TM_PAD_K2;  // K2 row tiles: one pad element per 32 (measur
 #ifndef TM_K2_WAVE
 #define TM_K2_WAVE 1
 #endif
-// K2 row transforms of 1024 points: one wavefront per row (measured 3%
+// K2 row transforms of 1024 points: one wavefront per row (measured 4%
 // faster there; slower for 384- and 768-point rows, which keep the
 // workgroup-wide transform)
 constexpr bool K2_WAVE = TM_K2_WAVE != 0;
@@ -67,7 +67,7 @@ constexpr bool K2_WAVE = TM_K2_WAVE != 0;
 #define TM_K2_SHUFFLE 1
 #endif
 // wavefront-owned 1024-point rows: the last Stockham exchange by lane swaps
-// instead of LDS (FP64 tiles; full product's K2 at n = 2^30 2% faster)
+// instead of LDS (FP64 tiles; full product's K2 at n = 2^30 3% faster)
 constexpr bool K2_SHUFFLE = TM_K2_SHUFFLE != 0;
 #ifndef TM_NT3
 #define TM_NT3 256
