@@ -83,6 +83,12 @@ constexpr int DPW = DPT * NT4;  // coefficients per workgroup in K4
 #define TM_K4_WAVES 8
 #endif
 constexpr int K4_WAVES = TM_K4_WAVES;  // K4 register bound: waves per SIMD
+#ifndef TM_K4_PREV_TOP
+#define TM_K4_PREV_TOP 1
+#endif
+// K4: carry into a workgroup from the previous workgroup's recomputed top
+// limb when that fixes it, before any look-back
+constexpr bool K4_PREV_TOP = TM_K4_PREV_TOP != 0;
 #ifndef TM_TILE1
 #define TM_TILE1 4096
 #endif
@@ -1298,6 +1304,9 @@ template <int LB, int NOUT, int OFF>
 __device__ __forceinline__ void back_chain(const KParams& p, const double* sq, int s0, int64_t k0,
                                            double (&acc)[NOUT])
 {
+    // every operation as written (no contraction), so that prev_top_carry's
+    // per-output recomputation gives the same bits
+#pragma clang fp contract(off)
     constexpr int NIN = NOUT + LB - 1;
 #pragma unroll
     for (int o = 0; o < NOUT; o++) acc[o] = 0.0;
@@ -1327,6 +1336,119 @@ __device__ __forceinline__ double real_at(const dfc* z, int64_t i)
     return df_to((i & 1) ? c.y : c.x);
 }
 
+// Carry function of one limb of S from its 128-bit sum T = thi 2^64 + tlo:
+// carry out = floor((T + cin) / 2^64) = A + [cin >= T'].  Every carry is
+// below 2^57 in magnitude (|c_i| < 2^51, at most 9 per limb), so a
+// threshold beyond that decides the carry alone: such functions are made
+// constant (T' = INT64_MAX).
+__device__ __forceinline__ CarryF limb_carry_fn(uint64_t tlo, int64_t thi)
+{
+    CarryF f;
+    if (tlo >= (1ull << 63)) {
+        f.A = thi;
+        f.T = tlo == (1ull << 63) ? INT64_MAX : (int64_t)(0 - tlo);
+    } else {
+        f.A = thi - 1;
+        f.T = -(int64_t)tlo;
+    }
+    if (f.T > K4_CMAX) {
+        f.T = INT64_MAX;
+    } else if (f.T < -K4_CMAX) {
+        f.A += 1;
+        f.T = INT64_MAX;
+    }
+    return f;
+}
+
+// Carry out of the previous workgroup's top limb (limb j0 - 1, j0 = the
+// first limb of this workgroup), from that workgroup's last DPT
+// coefficients recomputed here by one wavefront, lane t taking output t of
+// the previous workgroup's last thread: its inputs lie in this workgroup's
+// staged halo, and the sum runs over the same inputs in the same order with
+// the same operations as back_chain, so the values are the same bits.  The
+// coefficients that start in limb j0 - 1 are among them since b >= 8.
+// When that limb's carry function is constant it is the carry into this
+// workgroup, whatever lies further back, and the look-back is not needed;
+// pk = false otherwise, or when a value is not clearly rounded (then the
+// look-back decides).  For workgroups g >= 1 whose first index base <= N
+// (the previous one holds neither the wrap's edge indices nor the high
+// product's top index N); called by a whole wavefront.
+template <int KIND, int B>
+__device__ void prev_top_carry(const KParams& p, const double* sq, uint64_t base, int b, int lane,
+                               bool& pk, int64_t& pc)
+{
+#pragma clang fp contract(off)
+    constexpr int LB = KIND == K_FULL ? 1 : B ? LB_FIXED : LMAX;
+    constexpr int OFF = KIND == K_HI ? 1 : 0;
+    constexpr int NOUT = DPT + OFF;
+    constexpr double RMAG = 6755399441055744.0;
+    const uint64_t i0 = base - DPT;  // first index of the previous workgroup's last thread
+    const int o = lane < NOUT ? lane : NOUT - 1;
+    double x;
+    if constexpr (KIND == K_FULL) {
+        x = sq[padq(K4_HALO - DPT + o)] * p.bscale;
+    } else {
+        // back_chain's acc[o]: inputs e = o .. o + LB - 1 in that order, input
+        // e scaled by r = o + LB - 1 - e factors
+        const int s0 = K4_HALO - DPT - OFF - (LB - 1);
+        const int64_t k0 = (int64_t)i0 - OFF - (LB - 1);
+        const double x0 = (double)k0 * p.invN;
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < LB; d++) {
+            const int e = o + d;
+            const int r = LB - 1 - d;
+            double tau = sq[padq(s0 + e)] * p.bscale;
+            const double xk = fma((double)e, p.invN, x0);
+#pragma unroll
+            for (int q = 0; q < LB - 1; q++)
+                if (q < r) tau *= fma(p.nb[q][0], xk, p.nb[q][1]);
+            acc += tau;
+        }
+        if constexpr (KIND == K_LO) {
+            x = acc;
+        } else {
+            const double nxt = __shfl_down(acc, 1);
+            x = fma(-ldexp(1.0, -b), acc, nxt);
+        }
+    }
+    // rounding as in k4_body
+    const double xs = lane < DPT && i0 + lane < p.ncoef ? x : 0.0;
+    const double sh = xs + RMAG;
+    const double rr = sh - RMAG;
+    int64_t c = (int64_t)__double_as_longlong(sh) - (int64_t)__double_as_longlong(RMAG);
+    const bool clear = fabs(xs - rr) < 0.25 && fabs(xs) < 1125899906842624.0;
+    if (KIND == K_HI && lane < DPT) {
+        const uint64_t dm1 = p.off - 1;
+        const uint64_t ih = dm1 / (uint64_t)b;
+        if (ih == i0 + lane) c += 1ll << (dm1 - ih * (uint64_t)b);
+    }
+    pk = false;
+    pc = 0;
+    if (__ballot(!clear) != 0) return;
+    // limb j0 - 1: the coefficients i >= ia, summed in 128 bits
+    const int64_t j = (int64_t)(base * (uint64_t)b / 64) - 1;
+    const int64_t ia = (64 * j + b - 1) / b;
+    uint64_t tlo = 0;
+    int64_t thi = 0;
+#pragma unroll
+    for (int t = 0; t < DPT; t++) {
+        const int64_t ct = __shfl(c, t);
+        const int64_t i = (int64_t)i0 + t;
+        if (i >= ia) {
+            const int shf = (int)(i * b - 64 * j);
+            const uint64_t plo = (uint64_t)ct << shf;
+            const int64_t phi = shf ? ct >> (64 - shf) : (ct >> 63);
+            const uint64_t nlo = tlo + plo;
+            thi += phi + (nlo < plo ? 1 : 0);
+            tlo = nlo;
+        }
+    }
+    const CarryF f = limb_carry_fn(tlo, thi);
+    pk = f.T == INT64_MAX;
+    pc = f.A;
+}
+
 template <int KIND, bool DIAG, int B, typename C = double2>
 __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
 {
@@ -1334,6 +1456,8 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
     constexpr int LB = KIND == K_FULL ? 1 : B ? LB_FIXED : LMAX;
     __shared__ uint32_t s_g;
     __shared__ int64_t s_cin;
+    __shared__ uint32_t s_pk;  // the previous workgroup's top limb fixed the carry
+    __shared__ int64_t s_pc;   // (and that carry)
     __shared__ double s_thW;
     __shared__ double sq[padq(DPW + K4_HALO) + 1];
     __shared__ int64_t sWA[NW], sWT[NW];
@@ -1345,6 +1469,7 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
     const C* q = reinterpret_cast<const C*>(p.za);
 
     if (tid == 0) {
+        s_pk = 0;
         s_g = DIAG ? bk.x : atomicAdd(p.ticket, 1u);
         if (KIND == K_HI) s_thW = p.theta[0] * p.theta[1];
     }
@@ -1363,6 +1488,17 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
         sq[padq(e)] = (i >= 0 && i < (int64_t)p.N) ? real_at(q, i) : 0.0;
     }
     __syncthreads();
+    // the previous workgroup's top limb, while its inputs are staged (the
+    // last wavefront; the others meet it at the next barrier)
+    if (K4_PREV_TOP && !DIAG && wv == NW - 1 && g > 0 && base <= (uint64_t)p.N) {
+        bool pk;
+        int64_t pc;
+        prev_top_carry<KIND, B>(p, sq, base, b, lane, pk, pc);
+        if (lane == 0 && pk) {
+            s_pc = pc;
+            s_pk = 1;
+        }
+    }
 
     // x_i (see back_edge / back_chain) and rounded coefficients, with the guard
     double xv[DPT];
@@ -1508,23 +1644,7 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
                     tlo[k] = nlo;
                 }
             }
-            // carry out of limb j: floor((T_j + cin) / 2^64) = A + [cin >= T]
-            if (tlo[k] >= (1ull << 63)) {
-                fl[k].A = thi[k];
-                fl[k].T = tlo[k] == (1ull << 63) ? INT64_MAX : (int64_t)(0 - tlo[k]);
-            } else {
-                fl[k].A = thi[k] - 1;
-                fl[k].T = -(int64_t)tlo[k];
-            }
-            // every carry is below 2^57 in magnitude (|c_i| < 2^51, at most
-            // 9 per limb), so a threshold beyond that decides the carry
-            // alone: make such functions constant (T = INT64_MAX)
-            if (fl[k].T > K4_CMAX) {
-                fl[k].T = INT64_MAX;
-            } else if (fl[k].T < -K4_CMAX) {
-                fl[k].A += 1;
-                fl[k].T = INT64_MAX;
-            }
+            fl[k] = limb_carry_fn(tlo[k], thi[k]);
         }
     }
     CarryF f = fl[0];
@@ -1570,7 +1690,10 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
         for (int w2 = 1; w2 < NW; w2++) agg = compose(agg, CarryF{sWA[w2], sWT[w2]});
         uint64_t* st = p.status;
         int64_t cin = 0;
-        if (g > 0) {
+        // the previous workgroup's top limb usually fixes the carry alone
+        const bool known = K4_PREV_TOP && s_pk != 0;
+        if (known) cin = s_pc;
+        if (g > 0 && !known) {
             if (lane == 0) {
                 if (agg.T == INT64_MAX || agg.T == INT64_MIN) {
                     st_rlx(&st[2 * g + 0], pack62(3, apply(agg, 0)));
