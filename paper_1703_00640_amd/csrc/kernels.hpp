@@ -1215,10 +1215,79 @@ __device__ __forceinline__ uint64_t pack62(uint64_t state, int64_t v)
     return (state << 62) | ((uint64_t)v & ((1ull << 62) - 1));
 }
 __device__ __forceinline__ int64_t unpack62(uint64_t w) { return (int64_t)(w << 2) >> 2; }
+// Lane moves by DPP (data-parallel primitives, GFX9 controls): row_shr:d
+// (0x110 + d) within 16-lane rows, row_bcast:15 / row_bcast:31 (0x142 /
+// 0x143: the last lane of a row into the next row(s), rows chosen by ROWS),
+// wave_shr:1 (0x138), quad_perm (0x00..0xff), row_half_mirror (0x141) and
+// row_mirror (0x140).  A lane with no source, or in a row outside ROWS,
+// gets `old`.  They run at VALU speed, where ds_bpermute / ds_swizzle
+// shuffles take an LDS round trip per step.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ uint64_t dpp64(uint64_t old, uint64_t v)
+{
+    const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)old, (int)(uint32_t)v, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(old >> 32), (int)(uint32_t)(v >> 32), CTRL, ROWS,
+                                               0xf, false);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_keep(double v)  // lanes with no source keep v
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    return __longlong_as_double((long long)dpp64<CTRL, ROWS>(u, u));
+}
+
+// Maximum over the wavefront, returned in every lane: quad, half-row and
+// row mirrors, then the rows' maxima carried into lane 63 by the row
+// broadcasts, then read from lane 63.
+#ifndef TM_K4_DPP
+#define TM_K4_DPP 1
+#endif
 __device__ __forceinline__ double wave_max(double v)
 {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    return v;
+    if (!TM_K4_DPP) {
+        for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+        return v;
+    }
+    v = fmax(v, dpp_keep<0xb1>(v));        // quad_perm [1,0,3,2]
+    v = fmax(v, dpp_keep<0x4e>(v));        // quad_perm [2,3,0,1]
+    v = fmax(v, dpp_keep<0x141>(v));       // row_half_mirror
+    v = fmax(v, dpp_keep<0x140>(v));       // row_mirror
+    v = fmax(v, dpp_keep<0x142, 0xa>(v));  // row_bcast:15 into rows 1, 3
+    v = fmax(v, dpp_keep<0x143, 0xc>(v));  // row_bcast:31 into rows 2, 3
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Inclusive scan of carry functions over the wavefront (lane l ends with
+// f_l o ... o f_0): the rows of 16 by row shifts, then each row composed
+// after the rows below it by the row broadcasts.
+__device__ __forceinline__ CarryF wave_scan(CarryF f, int lane)
+{
+    if (!TM_K4_DPP) {
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t pa = __shfl_up(f.A, d), pt = __shfl_up(f.T, d);
+            if (lane >= d) f = compose(CarryF{pa, pt}, f);
+        }
+        return f;
+    }
+    const int lr = lane & 15;
+#define TM_SCAN_STEP(CTRL, ROWS, COND)                                             \
+    {                                                                              \
+        const CarryF q = {(int64_t)dpp64<CTRL, ROWS>(0, (uint64_t)f.A),            \
+                          (int64_t)dpp64<CTRL, ROWS>(0, (uint64_t)f.T)};           \
+        if (COND) f = compose(q, f);                                               \
+    }
+    TM_SCAN_STEP(0x111, 0xf, lr >= 1)
+    TM_SCAN_STEP(0x112, 0xf, lr >= 2)
+    TM_SCAN_STEP(0x114, 0xf, lr >= 4)
+    TM_SCAN_STEP(0x118, 0xf, lr >= 8)
+    TM_SCAN_STEP(0x142, 0xa, (lane & 16) != 0)
+    TM_SCAN_STEP(0x143, 0xc, (lane & 32) != 0)
+#undef TM_SCAN_STEP
+    return f;
 }
 
 // x_i, the value rounded to c_i (see tm_guard), from the LDS copy of q
@@ -1652,13 +1721,9 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
     for (int k = 1; k < MLPT; k++)
         if (k < nl) f = compose(f, fl[k]);
 
-    // inclusive scan of carry functions: within each wave by shuffles, then
-    // across the NW waves through LDS
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int64_t pa = __shfl_up(f.A, d), pt = __shfl_up(f.T, d);
-        if (lane >= d) f = compose(CarryF{pa, pt}, f);
-    }
+    // inclusive scan of carry functions: within each wave by DPP lane moves,
+    // then across the NW waves through LDS
+    f = wave_scan(f, lane);
     if (lane == 63) {
         sWA[wv] = f.A;
         sWT[wv] = f.T;
@@ -1673,7 +1738,8 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
     }
     if (have_pre) f = compose(pre, f);
     // exclusive prefix of this thread
-    const int64_t ea = __shfl_up(f.A, 1), et = __shfl_up(f.T, 1);
+    const int64_t ea = (int64_t)dpp64<0x138>(0, (uint64_t)f.A);  // wave_shr:1
+    const int64_t et = (int64_t)dpp64<0x138>(0, (uint64_t)f.T);
     CarryF excl = lane > 0 ? CarryF{ea, et} : pre;
     const bool have_excl = lane > 0 || have_pre;
 
