@@ -1641,7 +1641,9 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
         sGD[wv] = dmax;
         sGA[wv] = amax;
     }
-    __syncthreads();
+    // (read by the guard's publication after later barriers; the diagnostic
+    // variant publishes here)
+    if (DIAG) __syncthreads();
     // guard: one atomic per field and only when it raises the stored
     // maximum (non-negative doubles order like their bit patterns).  Done by
     // wave 1 during the look-back, off the other waves' path.
@@ -1849,11 +1851,13 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
             s_cin = cin;
         }
     }
-    __syncthreads();
-
-    // limb values with the true carry-in (the look-back ended with a
-    // barrier, so every read of sc is done and sS may reuse the space)
-    const int64_t cwg = s_cin;
+    // the carry into this workgroup: from the previous workgroup's top limb
+    // (known to every wave, no wait for wave 0), else from the look-back
+    // (after a barrier).  Every read of sc ended before the scan's barrier,
+    // so the limb values sS may reuse the space.
+    const bool cknown = K4_PREV_TOP && s_pk != 0;
+    if (!cknown) __syncthreads();
+    const int64_t cwg = cknown ? s_pc : s_cin;
     int64_t cin = have_excl ? apply(excl, cwg) : cwg;
     uint64_t* sS = reinterpret_cast<uint64_t*>(sq);
 #pragma unroll
