@@ -1551,10 +1551,22 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
 
     // stage q[base - HALO, base + DPW) (zero outside [0, N))
     if (tid == 0) sGF = 0;
-    for (int e = tid; e < DPW + K4_HALO; e += NT4) {
-        int64_t i = (int64_t)base - K4_HALO + e;
-        if (i < 0 && KIND != K_FULL) i += p.N;  // cyclic: wrapped terms of the maps
-        sq[padq(e)] = (i >= 0 && i < (int64_t)p.N) ? real_at(q, i) : 0.0;
+    if constexpr (std::is_same<C, double2>::value) {
+        // pairs (i, i + 1) with i even (base, K4_HALO and N are even): one
+        // 16-byte load of the packed result per pair
+        for (int e = 2 * tid; e < DPW + K4_HALO; e += 2 * NT4) {
+            int64_t i = (int64_t)base - K4_HALO + e;
+            if (i < 0 && KIND != K_FULL) i += p.N;  // cyclic: wrapped terms of the maps
+            const double2 z = (i >= 0 && i < (int64_t)p.N) ? q[i >> 1] : make_double2(0.0, 0.0);
+            sq[padq(e)] = z.x;
+            sq[padq(e + 1)] = z.y;
+        }
+    } else {
+        for (int e = tid; e < DPW + K4_HALO; e += NT4) {
+            int64_t i = (int64_t)base - K4_HALO + e;
+            if (i < 0 && KIND != K_FULL) i += p.N;
+            sq[padq(e)] = (i >= 0 && i < (int64_t)p.N) ? real_at(q, i) : 0.0;
+        }
     }
     __syncthreads();
     // the previous workgroup's top limb, while its inputs are staged (the
