@@ -267,14 +267,17 @@ __device__ __forceinline__ void tw_powers(C w, C* pw)
     for (int r = 2; r < R; r++) pw[r] = cmul(pw[r / 2], pw[r - r / 2]);
 }
 
-// radix of the next stage given the remaining length
+// radix of the next stage given the remaining length: 16 and 8 first, so
+// the first stage (which needs no twiddles) is the widest one and the small
+// odd radices come last, where their twiddles are few (384-point K2 rows:
+// 16, 8, 3 measured 5% faster than 3, 16, 8)
 constexpr int pick_radix(int rem)
 {
-    return rem % 3 == 0   ? 3
+    return rem % 16 == 0  ? 16
+           : rem % 8 == 0 ? 8
+           : rem % 3 == 0 ? 3
            : rem % 5 == 0 ? 5
            : rem % 7 == 0 ? 7
-           : rem % 16 == 0 ? 16
-           : rem % 8 == 0 ? 8
            : rem % 4 == 0 ? 4
                           : 2;
 }
