@@ -707,6 +707,24 @@ __device__ __forceinline__ C pointwise_bin(C Ya, C Yam, C Yb, C Ybm, C wk)
     return cadd(X, mul_mi<true>(Yv));  // X + i Yv
 }
 
+// A bin and its mirror from one unpacking: the mirror's even and odd
+// spectra are the conjugates of the bin's and so is its twiddle
+// (w^(M-k) = conj w^k), so its X and Yv are the conjugates too.
+template <typename C>
+__device__ __forceinline__ void pointwise_pair(C Ya, C Yam, C Yb, C Ybm, C wk, C& q, C& qm)
+{
+    C Ea = cscale(cadd(Ya, cconj(Yam)), 0.5);
+    C Oa = cscale(csub(Ya, cconj(Yam)), 0.5);
+    Oa = mul_mi<false>(Oa);
+    C Eb = cscale(cadd(Yb, cconj(Ybm)), 0.5);
+    C Ob = cscale(csub(Yb, cconj(Ybm)), 0.5);
+    Ob = mul_mi<false>(Ob);
+    C X = cadd(cmul(Ea, Eb), cmul(wk, cmul(Oa, Ob)));
+    C Yv = cadd(cmul(Ea, Ob), cmul(Oa, Eb));
+    q = cadd(X, mul_mi<true>(Yv));
+    qm = cadd(cconj(X), mul_mi<true>(cconj(Yv)));
+}
+
 // Row pairs of K2.  Row (k1, km) (k1 < L1, km < Lm) holds bins
 // k = k1 + L1 (km + Lm k2), k2 < L2, at positions ((k1 Lm + km) L2 + k2).
 // The mirror bin M - k lies in row (L1 - k1, Lm - 1 - km) at L2 - 1 - k2 when
@@ -825,28 +843,52 @@ __device__ __forceinline__ void k2_body(const KParams& p, const Blk bk)
 
     constexpr int PER = (2 * L2 + NT2 - 1) / NT2;
     const C wrow0 = to_elem<C>(cmul(wr0a, wr0b)), wrow1 = to_elem<C>(cmul(wr1a, wr1b));
-    C qv[PER];
+    if (!rr.self) {
+        // distinct rows: bin (row a, k2) with its mirror (row b, L2 - 1 - k2)
+        constexpr int PP = (L2 + NT2 - 1) / NT2;
+        C qa[PP], qb[PP];
 #pragma unroll
-    for (int t = 0; t < PER; t++) {
-        const int e = threadIdx.x + t * NT2;
-        if (e < 2 * L2) {
-            const int pr = e / L2, k2 = e % L2;
-            // self-mirrored rows pair with themselves (row (0, 0) in slot 0
-            // with k2 -> (L2 - k2) mod L2), distinct rows with each other
-            const int mk2 = rr.self && pr == 0 ? (L2 - k2) % L2 : L2 - 1 - k2;
-            const int mr = rr.self ? pr : 1 - pr;
-            qv[t] = pointwise_bin(rows[pidx<PAD2>((2 * pr) * L2 + k2)], rows[pidx<PAD2>((2 * mr) * L2 + mk2)],
-                                  rows[pidx<PAD2>((2 * pr + 1) * L2 + k2)], rows[pidx<PAD2>((2 * mr + 1) * L2 + mk2)],
-                                  cmul(pr ? wrow1 : wrow0, tw_half<L2>(twl, k2)));
+        for (int t = 0; t < PP; t++) {
+            const int k2 = threadIdx.x + t * NT2;
+            if (L2 % NT2 == 0 || k2 < L2) {
+                const int mk2 = L2 - 1 - k2;
+                pointwise_pair(rows[pidx<PAD2>(k2)], rows[pidx<PAD2>(2 * L2 + mk2)], rows[pidx<PAD2>(L2 + k2)],
+                               rows[pidx<PAD2>(3 * L2 + mk2)], cmul(wrow0, tw_half<L2>(twl, k2)), qa[t], qb[t]);
+            }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 #pragma unroll
-    for (int t = 0; t < PER; t++) {
-        const int e = threadIdx.x + t * NT2;
-        if (e < 2 * L2) {
-            const int pr = e / L2, k2 = e % L2;
-            rows[pidx<PAD2>((2 * pr) * L2 + k2)] = qv[t];
+        for (int t = 0; t < PP; t++) {
+            const int k2 = threadIdx.x + t * NT2;
+            if (L2 % NT2 == 0 || k2 < L2) {
+                rows[pidx<PAD2>(k2)] = qa[t];
+                rows[pidx<PAD2>(2 * L2 + L2 - 1 - k2)] = qb[t];
+            }
+        }
+    } else {
+        // the workgroup of the self-mirrored rows: one bin at a time (row
+        // (0, 0) in slot 0 pairs with itself with k2 -> (L2 - k2) mod L2, the
+        // other self-mirrored row with k2 -> L2 - 1 - k2)
+        C qv[PER];
+#pragma unroll
+        for (int t = 0; t < PER; t++) {
+            const int e = threadIdx.x + t * NT2;
+            if (e < 2 * L2) {
+                const int pr = e / L2, k2 = e % L2;
+                const int mk2 = pr == 0 ? (L2 - k2) % L2 : L2 - 1 - k2;
+                qv[t] = pointwise_bin(rows[pidx<PAD2>((2 * pr) * L2 + k2)], rows[pidx<PAD2>((2 * pr) * L2 + mk2)],
+                                      rows[pidx<PAD2>((2 * pr + 1) * L2 + k2)], rows[pidx<PAD2>((2 * pr + 1) * L2 + mk2)],
+                                      cmul(pr ? wrow1 : wrow0, tw_half<L2>(twl, k2)));
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < PER; t++) {
+            const int e = threadIdx.x + t * NT2;
+            if (e < 2 * L2) {
+                const int pr = e / L2, k2 = e % L2;
+                rows[pidx<PAD2>((2 * pr) * L2 + k2)] = qv[t];
+            }
         }
     }
     __syncthreads();
