@@ -1493,6 +1493,8 @@ __device__ void prev_top_carry(const KParams& p, const double* sq, uint64_t base
     constexpr int OFF = KIND == K_HI ? 1 : 0;
     constexpr int NOUT = DPT + OFF;
     constexpr double RMAG = 6755399441055744.0;
+    static_assert(DPT * 8 >= 64, "digits of b >= 8 bits: one limb's coefficients lie among the last DPT");
+    static_assert(NOUT <= 64 && K4_HALO >= DPT + OFF + LMAX - 1, "one lane per output, inputs in the halo");
     const uint64_t i0 = base - DPT;  // first index of the previous workgroup's last thread
     const int o = lane < NOUT ? lane : NOUT - 1;
     double x;
