@@ -945,8 +945,18 @@ __device__ __forceinline__ void mid_body(const KParams& p, const Blk bk)
     __shared__ C tile[padded(LM * W)];
     __shared__ C twl[twl_size(LM)];
     const uint32_t L2 = p.L2;
-    const uint32_t c0 = xcd_tile(bk.x, bk.nx) * W;
-    C* a = reinterpret_cast<C*>(bk.z ? p.zb : p.za) + (size_t)bk.y * p.R;
+    // tile and row of this workgroup: with both grid extents multiples of
+    // 8, the workgroups of one XCD (bk.x mod 8 under the round-robin
+    // dispatch) take whole rows of each group of eight rows, so one XCD
+    // streams contiguous row segments (4% faster than XCD-contiguous column
+    // tiles within every row for 384-point rows; equal for 1024)
+    uint32_t xt = xcd_tile(bk.x, bk.nx), yr = bk.y;
+    if (bk.nx % 8 == 0 && bk.ny % 8 == 0) {
+        xt = bk.x / 8 + (bk.nx / 8) * (bk.y % 8);
+        yr = (bk.y & ~7u) + bk.x % 8;
+    }
+    const uint32_t c0 = xt * W;
+    C* a = reinterpret_cast<C*>(bk.z ? p.zb : p.za) + (size_t)yr * p.R;
     const int tid = threadIdx.x;
     load_twl<LM, NTM>(twl, p.twm);
     // twiddle exponents on the R-th root, as exponents of the M-th root (x L1)
