@@ -26,7 +26,8 @@
 // tile; TM_DPT coefficients per K4 thread; TM_PAD_SHIFT LDS tile padding
 // (TM_PAD_K2 for K2's row tiles); TM_K2_WAVE wavefront-owned 1024-point K2
 // rows, TM_K2_SHUFFLE their last exchange by lane swaps; TM_K4_WAVES K4's
-// register bound.
+// register bound, TM_K4_PREV_TOP its carry from the previous workgroup's
+// recomputed top limb, TM_K4_DPP its wavefront scans by DPP lane moves.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
