@@ -1326,6 +1326,17 @@ __device__ __forceinline__ CarryF wave_scan(CarryF f, int lane)
         }
         return f;
     }
+    // a constant function (T = INT64_MAX) absorbs every function before it,
+    // so lane l ends with f_l when f_l is constant, and with f_l o f_(l-1)
+    // when only f_(l-1) is: while no two neighbouring lanes hold
+    // non-constant functions (the usual case) one lane shift is the scan
+    const bool nc = f.T != INT64_MAX;
+    const uint64_t m = __ballot(nc);
+    if ((m & (m << 1)) == 0) {
+        const CarryF q = {(int64_t)dpp64<0x138>(0, (uint64_t)f.A), (int64_t)dpp64<0x138>(0, (uint64_t)f.T)};
+        if (nc && lane > 0) f = compose(q, f);
+        return f;
+    }
     const int lr = lane & 15;
 #define TM_SCAN_STEP(CTRL, ROWS, COND)                                             \
     {                                                                              \
@@ -1606,7 +1617,15 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
 
     // stage q[base - HALO, base + DPW) (zero outside [0, N))
     if (tid == 0) sGF = 0;
-    if constexpr (std::is_same<C, double2>::value) {
+    if (std::is_same<C, double2>::value && base >= (uint64_t)K4_HALO && base + DPW <= p.N) {
+        // away from both ends: every index in range, no wrap
+        const double2* qh = reinterpret_cast<const double2*>(p.za) + (base - K4_HALO) / 2;
+        for (int e = 2 * tid; e < DPW + K4_HALO; e += 2 * NT4) {
+            const double2 z = qh[e >> 1];
+            sq[padq(e)] = z.x;
+            sq[padq(e + 1)] = z.y;
+        }
+    } else if constexpr (std::is_same<C, double2>::value) {
         // pairs (i, i + 1) with i even (base, K4_HALO and N are even): one
         // 16-byte load of the packed result per pair
         for (int e = 2 * tid; e < DPW + K4_HALO; e += 2 * NT4) {
@@ -1684,10 +1703,8 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
     int64_t c[DPT];
     double dmax = 0.0, amax = 0.0;
     uint32_t gflags = 0;
-#pragma unroll
-    for (int t = 0; t < DPT; t++) {
+    auto round_at = [&](int t, bool live) {
         const uint64_t i = i0 + t;
-        const bool live = i < p.ncoef;
         const double xs = live ? xv[t] : 0.0;
         const double sh = xs + RMAG;
         const double r = sh - RMAG;
@@ -1698,6 +1715,13 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
             p.dbg_c[i] = c[t];
             if (p.dbg_x) p.dbg_x[i] = xs;
         }
+    };
+    if (base + DPW <= p.ncoef) {  // every coefficient of the workgroup exists
+#pragma unroll
+        for (int t = 0; t < DPT; t++) round_at(t, true);
+    } else {
+#pragma unroll
+        for (int t = 0; t < DPT; t++) round_at(t, i0 + t < p.ncoef);
     }
     if (KIND != K_FULL && i0 == 0 && (c[0] & ((1ll << b) - 1)) != 0) gflags |= TM_GUARD_C0;
     // guard: reduce over the workgroup (published at the end)
@@ -1768,20 +1792,24 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
         fl[k] = CarryF{0, INT64_MAX};
         if (k < nl) {
             const int j = j0 + k;
+            // c_i, ia <= i < ib, start in limb j: at most ceil(64 / b) of them
             const int ia = (64 * j + b - 1) / b, ib = (64 * (j + 1) + b - 1) / b;
+            unsigned __int128 tacc = 0;
 #pragma unroll
-            for (int u = 0; u < (64 + 7) / 8 + 1; u++) {
+            for (int u = 0; u < (B ? (64 + B - 1) / B : 8); u++) {
                 const int i = ia + u;
                 if (i < ib) {
+                    // c_i 2^sh as a 128-bit two's-complement term: the low
+                    // word c_i << sh, the high word floor(c_i 2^sh / 2^64)
                     const int64_t cv = sc[padq(i)];
                     const int sh = i * b - 64 * j;
                     const uint64_t plo = (uint64_t)cv << sh;
-                    const int64_t phi = sh ? cv >> (64 - sh) : (cv >> 63);
-                    const uint64_t nlo = tlo[k] + plo;
-                    thi[k] += phi + (nlo < plo ? 1 : 0);
-                    tlo[k] = nlo;
+                    const uint64_t phi = (uint64_t)((cv >> 1) >> (63 - sh));
+                    tacc += ((unsigned __int128)phi << 64) | plo;
                 }
             }
+            tlo[k] = (uint64_t)tacc;
+            thi[k] = (int64_t)(uint64_t)(tacc >> 64);
             fl[k] = limb_carry_fn(tlo[k], thi[k]);
         }
     }
@@ -1798,12 +1826,14 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
         sWT[wv] = f.T;
     }
     __syncthreads();
+    // prefix of the waves below, from the nearest one down, stopping at the
+    // first constant composition (which the waves further down cannot change)
     CarryF pre = {0, INT64_MAX};
-    bool have_pre = false;
-    for (int w2 = 0; w2 < wv; w2++) {
+    const bool have_pre = wv > 0;
+    for (int w2 = wv - 1; w2 >= 0; w2--) {
         const CarryF t = {sWA[w2], sWT[w2]};
-        pre = have_pre ? compose(pre, t) : t;
-        have_pre = true;
+        pre = w2 == wv - 1 ? t : compose(t, pre);
+        if (pre.T == INT64_MAX) break;
     }
     if (have_pre) f = compose(pre, f);
     // exclusive prefix of this thread
@@ -1821,8 +1851,8 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
     // are carries (|c| < 2^53) and thresholds clamped to +-2^61, which act
     // as +-infinity for such carries.
     if (wv == 0) {
-        CarryF agg = {sWA[0], sWT[0]};
-        for (int w2 = 1; w2 < NW; w2++) agg = compose(agg, CarryF{sWA[w2], sWT[w2]});
+        CarryF agg = {sWA[NW - 1], sWT[NW - 1]};
+        for (int w2 = NW - 2; w2 >= 0 && agg.T != INT64_MAX; w2--) agg = compose(CarryF{sWA[w2], sWT[w2]}, agg);
         uint64_t* st = p.status;
         int64_t cin = 0;
         // the previous workgroup's top limb usually fixes the carry alone
