@@ -51,7 +51,7 @@ constexpr int NT2 = TM_NT2;     // threads per K2 workgroup
 constexpr int NTM = TM_NTM;     // threads per middle-pass workgroup
 constexpr int LMAX = 9;         // largest supported series length lambda
 #ifndef TM_NT4
-#define TM_NT4 512
+#define TM_NT4 1024
 #endif
 #ifndef TM_PAD_K2
 #define TM_PAD_K2 5
@@ -572,19 +572,38 @@ __device__ __forceinline__ void k1_body(const KParams& p, const Blk bk)
     if (op == 0) clear_state(p, bk.x * NT1 + tid, bk.nx * NT1);
     if (KIND == K_HI && bk.x == 0 && tid <= (int)p.jmax && tid <= (int)p.N)
         s_th[tid] = ldexp((double)bal_digit(p, x, (int64_t)p.N - tid, p.digits, true), -tid * p.b);
+    // When a row of the tile spans a whole number of limbs (2 R b bits a
+    // multiple of 64), every row's digit window starts at the same bit
+    // offset rel_u and row j1's window at limb l_u + j1 (2 R b / 64).
+    int64_t l_u;
+    int rel_u;
+    row_window(p, 2 * (int64_t)c0 - LO, l_u, rel_u);
+    const uint64_t row_bits = 2ull * L2 * (uint64_t)(B ? B : p.b);
+    const int64_t row_limbs = (int64_t)(row_bits >> 6);
+    // ... and if every staged limb lies below the operand's top limb, no
+    // bounds checks or top-limb mask are needed
+    const bool inner = (row_bits & 63) == 0 && l_u >= 0 && l_u + (L1 - 1) * row_limbs + NLW < (int64_t)p.L;
     if constexpr (STAGE) {
         uint64_t* slimb = reinterpret_cast<uint64_t*>(tile);
         constexpr int PL = (L1 * NLW + NT1 - 1) / NT1;
         uint64_t lv[PL];
+        if (inner) {
 #pragma unroll
-        for (int q = 0; q < PL; q++) {
-            const int e = tid + q * NT1;
-            if (L1 * NLW % NT1 == 0 || e < L1 * NLW) {
-                const int row = e / NLW, i = e % NLW;
-                int64_t l0;
-                int rel0;
-                row_window(p, 2 * ((int64_t)row * L2 + c0) - LO, l0, rel0);
-                lv[q] = limb_at(p, x, l0 + i);
+            for (int q = 0; q < PL; q++) {
+                const int e = tid + q * NT1;
+                if (L1 * NLW % NT1 == 0 || e < L1 * NLW) lv[q] = x[l_u + (e / NLW) * row_limbs + e % NLW];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < PL; q++) {
+                const int e = tid + q * NT1;
+                if (L1 * NLW % NT1 == 0 || e < L1 * NLW) {
+                    const int row = e / NLW, i = e % NLW;
+                    int64_t l0;
+                    int rel0;
+                    row_window(p, 2 * ((int64_t)row * L2 + c0) - LO, l0, rel0);
+                    lv[q] = limb_at(p, x, l0 + i);
+                }
             }
         }
 #pragma unroll
@@ -617,8 +636,8 @@ __device__ __forceinline__ void k1_body(const KParams& p, const Blk bk)
             if (fast) {
                 if constexpr (STAGE) {
                     int64_t l0;
-                    int rel0;
-                    row_window(p, kf, l0, rel0);
+                    int rel0 = rel_u;
+                    if (!inner) row_window(p, kf, l0, rel0);
                     const uint64_t* sl = reinterpret_cast<const uint64_t*>(tile) + j1 * NLWP;
                     if constexpr (B > 0)
                         row_digits_fixed<ND, B, NLW>(sl, rel0, d);
@@ -1471,7 +1490,7 @@ __device__ __forceinline__ double real_at(const dfc* z, int64_t i)
 
 // Carry function of one limb of S from its 128-bit sum T = thi 2^64 + tlo:
 // carry out = floor((T + cin) / 2^64) = A + [cin >= T'].  Every carry is
-// below 2^57 in magnitude (|c_i| < 2^51, at most 9 per limb), so a
+// below 2^57 in magnitude (|c_i| < 2^51, at most 8 per limb), so a
 // threshold beyond that decides the carry alone: such functions are made
 // constant (T' = INT64_MAX).
 __device__ __forceinline__ CarryF limb_carry_fn(uint64_t tlo, int64_t thi)
@@ -1992,9 +2011,11 @@ __device__ __forceinline__ void k4_body(const KParams& p, const Blk bk)
     }
 }
 
-// eight waves per SIMD (four workgroups per CU, as the LDS allows): the
-// register bound this sets makes the high and full products' K4 about 12%
-// faster at n = 2^30
+// eight waves per SIMD (two 1024-thread workgroups per CU, as the LDS
+// allows).  Every workgroup takes one ticket, an atomic on a single address
+// that serialises at roughly 13 ns per ticket; 8192 coefficients per
+// workgroup keep that below the kernel's other work (with 4096 it bounded
+// the full product's K4 at n = 2^30)
 template <int KIND, bool DIAG, int B, typename C = double2>
 __global__ __launch_bounds__(NT4, K4_WAVES) void k4_backmap_carry(KParams p)
 {

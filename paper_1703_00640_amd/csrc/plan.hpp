@@ -26,7 +26,7 @@ constexpr int B_FULL = 16;           // digit size of the full product
 constexpr uint64_t TRUNC_MIN_BITS = 1025;  // below: full product + extraction
 constexpr uint32_t L2_MAX = 1024, L1_MAX = 4096, LM_MAX = 256;
 #ifndef TM_NT4
-#define TM_NT4 512
+#define TM_NT4 1024
 #endif
 #ifndef TM_DPT
 #define TM_DPT 8
