@@ -93,9 +93,9 @@ def stored_traffic(log2n):
 def pmc_pass(n_bits, reps=2):
     """Workload for rocprofv3 runs (kernel trace and counter passes): the
     autotuner's timing runs for every kind (the benchmark's FFT splits) and
-    one untimed product of each kind, then a marker dispatch (a fill of a
-    16-bit integer tensor, the only one in the run), then `reps` products of
-    each kind, then a plain 256 MiB device copy (the calibration kernel for
+    untimed products of each kind, then a marker dispatch (a fill of a
+    16-bit integer tensor, the only one in the run), then `reps` steps of one
+    product of each kind, then a plain 256 MiB device copy (the calibration kernel for
     FETCH_SIZE and WRITE_SIZE).
     Summaries take the dispatches between the marker and the copy."""
     import torch
@@ -110,12 +110,16 @@ def pmc_pass(n_bits, reps=2):
         tm.autotune(k, n_bits)  # the same FFT split as the benchmark
     ws = {k: torch.empty(tm.plan(k, n_bits)["workspace_bytes"], dtype=torch.uint8, device=dev)
           for k in kinds}
-    for k in kinds:  # one untimed product of each kind, so no kind runs first cold
-        tm.mul(k, du, dv, n_bits, workspace=ws[k])
+    # untimed steps first, so no kind runs cold (the VALU-bound kernels of a
+    # kind run back to back after another kind's took several launches to
+    # settle; interleaved steps, as in the benchmark, do not show this)
+    for _ in range(max(reps, 8)):
+        for k in kinds:
+            tm.mul(k, du, dv, n_bits, workspace=ws[k])
     torch.cuda.synchronize()
     torch.full((1,), 3, dtype=torch.int16, device=dev)  # marker
-    for k in kinds:
-        for _ in range(reps):
+    for _ in range(reps):  # interleaved like the benchmark's step
+        for k in kinds:
             tm.mul(k, du, dv, n_bits, workspace=ws[k])
     a = torch.ones(1 << 25, dtype=torch.float64, device=dev)
     b = torch.empty_like(a)
