@@ -562,8 +562,9 @@ def main():
         pmc_pass(1 << args.log2n, args.steps)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(independent products would shard by request; nothing here splits one product "
+              "over several GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import torch
