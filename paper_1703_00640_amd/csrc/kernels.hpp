@@ -612,6 +612,24 @@ __device__ __forceinline__ void k1_body(const KParams& p, const Blk bk)
             if (L1 * NLW % NT1 == 0 || e < L1 * NLW) slimb[(e / NLW) * NLWP + e % NLW] = lv[q];
         }
     }
+    // Row 0 of tile 0 of a truncated product touches index 0: its map takes
+    // the term-by-term form with cyclic indices.  Its digits are read here,
+    // one per thread, while the staging loads are in flight, and its 2W
+    // outputs are formed by 2W threads below (one thread doing all of them
+    // cost about 5 us at n = 2^16).
+    const bool erow = KIND != K_FULL && c0 == 0;
+    __shared__ int32_t s_ed[ND];
+    __shared__ double s_efn;
+    __shared__ double s_eo[2 * W];
+    static_assert(2 * W <= NT1 && ND < NT1, "one thread per edge digit and output");
+    if (erow) {
+        if (tid < ND) {
+            int64_t k = tid - (int64_t)LO;  // kf + tid with kf = -LO
+            if (k < 0) k += p.N;
+            s_ed[tid] = (int32_t)bal_digit(p, x, k, p.digits, false);
+        }
+        if (KIND == K_HI && tid == ND) s_efn = (double)bal_digit(p, x, p.N, p.digits, true);
+    }
     __syncthreads();
     if (KIND == K_HI && bk.x == 0 && tid == 0) {
         // theta = rho^-N F(rho), rho ~ 2^b: sum_j 2^(-jb) F_(N-j), j <= jmax
@@ -624,11 +642,26 @@ __device__ __forceinline__ void k1_body(const KParams& p, const Blk bk)
     // take the fast path; the others the term-by-term one
     const int64_t kf_min = KIND == K_HI ? (int64_t)p.jmax : 0;
     const int64_t top = (int64_t)p.digits - 1;
+    if (erow && tid < 2 * W) {
+        // output j = tid of the row, as row_map_edge forms it
+        const uint32_t j = (uint32_t)tid;
+        double sj = 0.0;
+#pragma unroll
+        for (int r = 0; r < LB; r++) {
+            if (r < p.lam) {
+                const uint32_t k = j >= (uint32_t)r ? j - r : j + p.N - r;
+                double f = (double)s_ed[tid - r + LO];
+                if (KIND == K_HI && k < p.jmax) f += ldexp(s_efn, -(int)k * p.b);
+                sj = fma(coef_fwd<KIND>(p, k, r), f, sj);
+            }
+        }
+        s_eo[tid] = sj;
+    }
     double2 g[RPT][W];
 #pragma unroll
     for (int rr = 0; rr < RPT; rr++) {
         const int j1 = tid + rr * NT1;
-        if (L1 % NT1 == 0 || j1 < L1) {
+        if ((L1 % NT1 == 0 || j1 < L1) && !(erow && j1 == 0)) {
             const uint32_t m0 = (uint32_t)j1 * L2 + c0;
             const int64_t kf = 2 * (int64_t)m0 - LO;
             const bool fast = kf >= kf_min && (KIND != K_FULL || kf + ND <= top);
@@ -666,15 +699,16 @@ __device__ __forceinline__ void k1_body(const KParams& p, const Blk bk)
             }
         }
     }
-    if constexpr (STAGE) __syncthreads();
+    if (STAGE || erow) __syncthreads();
 #pragma unroll
     for (int rr = 0; rr < RPT; rr++) {
         const int j1 = tid + rr * NT1;
-        if (L1 % NT1 == 0 || j1 < L1) {
+        if ((L1 % NT1 == 0 || j1 < L1) && !(erow && j1 == 0)) {
 #pragma unroll
             for (int c = 0; c < W; c++) tile[pidx(j1 * W + c)] = to_elem<C>(g[rr][c]);
         }
     }
+    if (erow && tid < W) tile[pidx(tid)] = to_elem<C>(make_double2(s_eo[2 * tid], s_eo[2 * tid + 1]));
     __syncthreads();
     tile_fft<L1, W, NT1, false, true>(tile, twl);
     TwSeq<PER, C> tws;
